@@ -1,0 +1,179 @@
+"""Benchmark: batched G^2 CI tests of PC-stable skeleton learning on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2]
+
+A step is one complete skeleton search (every depth of Algorithm 1: queue
+build, all CI tests, removals) over one synthetic dataset already resident in
+device memory.  The default workload is the 60-variable, 50,000-row network
+(the configuration the plain-versus-batched metric is quoted on).  Prints one
+JSON line; ``value`` is CI tests per second, counting the tests of the
+sequential order (per edge, up to and including its first accepting test).
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _sum(stats, key):
+    return sum(s[key] for s in stats)
+
+
+def _stats_of(bns, h):
+    sk = bns.collect(h)
+    return sk, sk.stats
+
+
+def cpu_baseline(datasets, budget_s=10.0):
+    """The oracle (single thread) on the same workload, repeated up to ~budget_s."""
+    import oracle
+    oracle.lib()
+    tests, t0, runs = 0, time.perf_counter(), 0
+    while True:
+        for ds in datasets:
+            r = oracle.pc_skeleton(ds.data, ds.cards, ds.alpha, ds.max_depth)
+            tests += sum(r.tests)
+        runs += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or runs >= 50:
+            break
+    return dict(value=tests / el, unit="CI tests/s", cores=1, kind="oracle",
+                sample=f"{runs} full run(s) of the workload, single thread, {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--precision", type=int, default=0, help="0 FP32+FP64 recheck, 1 FP64")
+    ap.add_argument("--lds-bytes", type=int, default=0)
+    ap.add_argument("--wg-per-cu", type=int, default=0)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2212_04259_amd as bns
+    from bnsynth import make_config
+    from bnsynth.generate import CONFIGS
+
+    torch.cuda.set_device(0)
+    dss = make_config(a.config)
+    # Inputs resident in device memory before the timed region.
+    handles = [bns.bns_dataset_create(d.data, d.cards) for d in dss]
+    alphas = [d.alpha for d in dss]
+    maxd = [d.max_depth for d in dss]
+    opt = bns.bns_options_default(precision=a.precision, lds_bytes=a.lds_bytes,
+                                  wg_per_cu=a.wg_per_cu)
+
+    def step(o):
+        if len(handles) == 1:
+            return [bns.skeleton_handle(handles[0], alphas[0], maxd[0], o)]
+        return bns.skeleton_batch_handles(handles, alphas, maxd, o)
+
+    for _ in range(a.warmup):
+        for h in step(opt):
+            bns.free_skeleton(h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        for h in step(opt):
+            bns.free_skeleton(h)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = 1e3 * el / a.steps
+
+    # Counters of one more (untimed) step, with events around each depth's
+    # persistent test launch for the roofline of that kernel.
+    topt = bns.bns_options_default(precision=a.precision, lds_bytes=a.lds_bytes,
+                                   wg_per_cu=a.wg_per_cu, timing=1)
+    hs = step(topt)
+    sks = [bns.collect(h) for h in hs]
+    stats = sks[0].stats          # a multi-dataset search shares one set of counters
+    required = _sum(stats, "tests_required")
+    executed = _sum(stats, "tests_executed")
+    rechecks = _sum(stats, "rechecks")
+    obytes = _sum(stats, "operand_bytes")
+    ksec = _sum(stats, "kernel_seconds")
+    m_total = sum(d.n_samples for d in dss)
+    rows_per_test = m_total / len(dss)
+    launches = len(stats)
+    achieved = (obytes / launches) / (ksec / launches) / 1e9 if ksec > 0 else None
+
+    out = {
+        "metric": "CI tests/sec (batched, same skeleton as the FP64 oracle)",
+        "value": required / (ms * 1e-3),
+        "unit": "CI tests/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {
+            "workload": CONFIGS[a.config]["name"],
+            "datasets": len(dss),
+            "n_vars": [d.n_vars for d in dss] if len(dss) > 1 else dss[0].n_vars,
+            "n_samples": m_total,
+            "alpha": alphas[0],
+            "max_depth": maxd[0],
+            "g2_arithmetic": "fp64" if a.precision == 1 else "fp32 + fp64 recheck",
+            "form": "batched persistent per-depth launch",
+        },
+        "tests_required_per_step": required,
+        "tests_executed_per_step": executed,
+        "waste_ratio": executed / required - 1.0 if required else 0.0,
+        "recheck_fraction": rechecks / executed if executed else 0.0,
+        "sample_rows_per_s": required * rows_per_test / (ms * 1e-3),
+        "depths": launches,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_depth_tests",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": None,
+            "launches": launches,
+            "kernel_ms_per_step": ksec * 1e3,
+            "operand_bytes_per_step": obytes,
+        },
+    }
+
+    if not a.no_plain and len(dss) == 1:
+        popt = bns.bns_options_default(form=bns.BNS_FORM_PLAIN, precision=1)
+        t0 = time.perf_counter()
+        h = bns.skeleton_handle(handles[0], alphas[0], maxd[0], popt)
+        torch.cuda.synchronize()
+        pel = time.perf_counter() - t0
+        psk = bns.collect(h)
+        same = (psk.adj == sks[0].adj).all() and psk.sepsets == sks[0].sepsets
+        preq = _sum(psk.stats, "tests_required")
+        out["plain_form"] = {"value": preq / pel, "unit": "CI tests/s", "ms_per_step": pel * 1e3,
+                             "same_skeleton_and_sepsets": bool(same)}
+        out["speedup_vs_plain"] = out["value"] / out["plain_form"]["value"]
+
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(dss)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,216 @@
+/*
+ * bns.h -- C ABI of the MI355X (gfx950) batched G^2 conditional-independence
+ * engine for PC-stable skeleton learning.
+ *
+ * Method: Jiang, Wen, Mian, "Fast Parallel Bayesian Network Structure
+ * Learning".  The library runs step 1 of PC-stable (Section III-C,
+ * Algorithm 1): starting from the complete undirected graph, at depth
+ * d = 0, 1, 2, ... every surviving edge (V_i, V_j) is tested for conditional
+ * independence given every size-d subset S of the frozen adjacency sets
+ * a(V_i)\{V_j}, then a(V_j)\{V_i} (the grouping of Section IV-C), in
+ * lexicographic order (Section IV-C), until one test accepts; the edge is then
+ * removed and S is its separating set.  Depth 0 runs one marginal test per
+ * pair (Section IV-B).  Each test is the G^2 test of Section III-B.
+ *
+ * Conventions shared by every entry point
+ *   - Data layout: variable-major ("transposed") uint8 columns, as in the
+ *     cache-friendly storage of Section IV-C: value of variable v in sample s
+ *     at data[v * ld + s], with ld = n_samples for host buffers.  Values must
+ *     lie in [0, cards[v]); cards[v] in [1, 255].
+ *   - Contingency table cell of (x, y, z_1..z_d):
+ *       cell = x + r_X * (y + r_Y * zc),  zc = sum_k z_k * prod_{l<k} r_{z_l}
+ *     (first conditioning variable fastest).
+ *   - G^2 = 2 sum_{xyz} N_xyz ln(N_xyz / E_xyz), E_xyz = N_x+z N_+yz / N_++z,
+ *     cells with N_xyz = 0 contribute 0 (Section III-B; natural log).
+ *   - df = (r_X - 1)(r_Y - 1) prod_k r_{z_k}, from the declared cards, with no
+ *     adjustment for empty cells (Section III-B gives the first two factors;
+ *     the conditioning factor is the standard one for a stratified test).
+ *   - p = Q(df / 2, G^2 / 2), the chi-square upper tail, always in FP64;
+ *     df = 0 gives p = 1.  Independence is declared iff p > alpha (strict).
+ *   - Sepset choice: among the tests of an edge in the order above, the first
+ *     accepting one; parallel forms reproduce exactly this choice.
+ *   - Counts are exact (int32 per cell; n_samples < 2^31).
+ *   - Errors: every entry point returns a bns_status; on failure nothing is
+ *     written to caller outputs beyond what the function documents, and
+ *     bns_last_error() describes the failure.  No exception crosses the ABI.
+ *   - Ownership: input buffers are borrowed for the duration of the call.
+ *     Handles (bns_dataset, bns_skeleton) are owned by the library until the
+ *     matching *_free.  Output arrays are allocated by the caller.
+ *   - Device and streams: work runs on the HIP device that is current on the
+ *     calling thread when the dataset is created; opt->stream selects the HIP
+ *     stream (NULL = the device's default stream).  Calls on one device are
+ *     serialised by the library; handles are not thread-safe.
+ */
+#ifndef BNS_H
+#define BNS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BNS_VERSION 1
+
+typedef enum bns_status {
+    BNS_OK = 0,
+    BNS_E_INVALID_ARG = 1,      /* NULL pointer, bad size, alpha not in (0,1), ... */
+    BNS_E_VALUE_RANGE = 2,      /* a data value >= its variable's cardinality */
+    BNS_E_TABLE_TOO_LARGE = 3,  /* a test's table exceeds the supported cell count */
+    BNS_E_NOMEM = 4,            /* device or host allocation failed */
+    BNS_E_DEVICE = 5,           /* no usable device, or a HIP call failed */
+    BNS_E_INTERNAL = 6
+} bns_status;
+
+/* Execution form of the skeleton search. */
+enum {
+    BNS_FORM_BATCHED = 0, /* device-resident per-depth work queue, one persistent launch per depth */
+    BNS_FORM_PLAIN = 1    /* host walks the tests in order; one sample-parallel launch per test */
+};
+
+/* Arithmetic of the G^2 log-sum (counts are always exact integers and the
+ * p-value is always FP64). */
+enum {
+    BNS_PREC_FP32_RECHECK = 0, /* FP32 G^2; FP64 re-evaluation near alpha */
+    BNS_PREC_FP64 = 1          /* FP64 G^2 */
+};
+
+typedef struct bns_options {
+    int32_t form;          /* BNS_FORM_*; default BATCHED */
+    int32_t precision;     /* BNS_PREC_*; default FP32_RECHECK */
+    double recheck_band;   /* FP32 mode: decisions with |p - alpha| < band (or within the
+                              propagated FP32 error bound) are re-evaluated in FP64;
+                              default 1e-3 */
+    int32_t lds_bytes;     /* LDS budget per workgroup for tables; 0 = default */
+    int32_t wg_per_cu;     /* persistent-grid workgroups per compute unit; 0 = default */
+    int32_t use_graph;     /* batched form: replay the per-depth launch sequence as a
+                              hipGraph; default 1 */
+    int32_t timing;        /* record HIP events around each depth's test launch; the
+                              durations appear in bns_depth_stats.kernel_seconds */
+    int32_t reserved[8];   /* must be zero */
+    void *stream;          /* hipStream_t; NULL = default stream */
+} bns_options;
+
+/* Fills *opt with the defaults.  opt must not be NULL. */
+void bns_options_default(bns_options *opt);
+
+/* Human-readable description of the last failure on the calling thread; valid
+ * until the next call into the library on this thread.  Never NULL. */
+const char *bns_last_error(void);
+
+/* ---------------------------------------------------------------------- */
+/* Datasets resident in device memory                                     */
+/* ---------------------------------------------------------------------- */
+typedef struct bns_dataset bns_dataset;
+
+/* Copies host data (uint8 [n_vars][n_samples], row v = variable v) and cards
+ * (uint8 [n_vars]) to the current device.  Every value is checked against its
+ * cardinality; the first offending (variable, sample) is reported as
+ * BNS_E_VALUE_RANGE.  n_samples in [1, 2^31 - 1], n_vars in [2, 65535]. */
+bns_status bns_dataset_create(const uint8_t *data, int64_t n_samples, int32_t n_vars,
+                              const uint8_t *cards, bns_dataset **out);
+
+/* Wraps device memory owned by the caller (e.g. a torch tensor): value of
+ * variable v in sample s at d_data[v * ld + s].  d_data must be 16-byte aligned
+ * and ld a multiple of 16 with ld >= n_samples; the memory must outlive the
+ * handle.  cards is a host array.  Values are checked on the device. */
+bns_status bns_dataset_wrap_device(const uint8_t *d_data, int64_t ld, int64_t n_samples,
+                                   int32_t n_vars, const uint8_t *cards, bns_dataset **out);
+
+void bns_dataset_free(bns_dataset *ds);
+
+/* ---------------------------------------------------------------------- */
+/* Batched CI tests (no PC control)                                       */
+/* ---------------------------------------------------------------------- */
+
+/* One test I(x, y | z): the conditioning variables are
+ * z_pool[z_offset .. z_offset + n_z). */
+typedef struct bns_ci_test {
+    int32_t x, y, n_z, z_offset;
+} bns_ci_test;
+
+/* Result flag bits of bns_ci_batch. */
+enum {
+    BNS_CI_INDEPENDENT = 1, /* p > alpha */
+    BNS_CI_RECHECKED = 2    /* FP32 mode: decided by the FP64 re-evaluation */
+};
+
+/* Runs n_tests G^2 tests on ds as given (Section III-B), in the precision of
+ * opt->precision.  All pointers are host pointers; outputs have n_tests
+ * entries: g2 (the statistic the decision used: FP64 when rechecked or in FP64
+ * mode), df, p, flags.  Any output may be NULL.  tables_out, when not NULL,
+ * receives each test's exact counts at tables_out[table_offsets[t] ..
+ * + r_x r_y prod r_z) in the cell layout above (table_offsets must then be
+ * given).  Tests must have x != y, z disjoint from {x, y}, ids in range;
+ * violations give BNS_E_INVALID_ARG before any device work. */
+bns_status bns_ci_batch(const bns_dataset *ds, const bns_ci_test *tests, int64_t n_tests,
+                        const int32_t *z_pool, int64_t z_pool_len, double alpha,
+                        const bns_options *opt, double *g2, int64_t *df, double *p,
+                        int32_t *flags, int32_t *tables_out, const int64_t *table_offsets);
+
+/* ---------------------------------------------------------------------- */
+/* PC-stable skeleton (Algorithm 1)                                       */
+/* ---------------------------------------------------------------------- */
+typedef struct bns_skeleton bns_skeleton;
+
+/* Per-depth counters of a skeleton search. */
+typedef struct bns_depth_stats {
+    int32_t depth;
+    int32_t reserved;
+    int64_t edges;           /* edges alive when the depth started */
+    int64_t tests_required;  /* tests in the canonical sequential order: per edge, up to
+                                and including its first accepting test */
+    int64_t tests_executed;  /* tests run, including speculative ones */
+    int64_t removed;         /* edges removed at this depth */
+    int64_t rechecks;        /* FP32 decisions re-evaluated in FP64 */
+    int64_t tickets;         /* work items scheduled (batched form) */
+    double operand_bytes;    /* sum over executed tests of (d + 2) * n_samples */
+    double kernel_seconds;   /* test-launch device time (opt->timing), else 0 */
+} bns_depth_stats;
+
+/* Learns the skeleton of one dataset.  alpha in (0, 1); max_depth >= -1
+ * (depths 0..max_depth; -1 = until no edge has a conditioning set of size d).
+ * Host data as in bns_dataset_create. */
+bns_status bns_pc_skeleton(const uint8_t *data, int64_t n_samples, int32_t n_vars,
+                           const uint8_t *cards, double alpha, int32_t max_depth,
+                           const bns_options *opt, bns_skeleton **out);
+
+/* Same, on a dataset already resident on the device. */
+bns_status bns_pc_skeleton_dataset(const bns_dataset *ds, double alpha, int32_t max_depth,
+                                   const bns_options *opt, bns_skeleton **out);
+
+/* Learns the skeletons of n_problems independent datasets together, one
+ * launch per depth covering all of them (batched form only).  alpha and
+ * max_depth are per problem; outs receives n_problems handles. */
+bns_status bns_pc_skeleton_batch(const bns_dataset *const *ds, int32_t n_problems,
+                                 const double *alpha, const int32_t *max_depth,
+                                 const bns_options *opt, bns_skeleton **outs);
+
+int32_t bns_skeleton_n_vars(const bns_skeleton *sk);
+
+/* adj: n_vars * n_vars uint8, adj[i * n + j] = 1 iff edge i - j survived. */
+bns_status bns_skeleton_adjacency(const bns_skeleton *sk, uint8_t *adj);
+
+/* Sepset of pair (i, j) (either order).  *len = -1 when the edge was kept,
+ * else its size (= removal depth); up to cap members written, ascending.
+ * removal_depth may be NULL. */
+bns_status bns_skeleton_sepset(const bns_skeleton *sk, int32_t i, int32_t j, int32_t *members,
+                               int32_t cap, int32_t *len, int32_t *removal_depth);
+
+/* Bulk export: depth[i * n + j] = removal depth or -1 (n_vars * n_vars int32);
+ * sep_off[i * n + j] = offset of the pair's sepset in pool or -1; pool receives
+ * up to pool_cap members; *pool_len = members needed.  depth, sep_off and pool
+ * may each be NULL. */
+bns_status bns_skeleton_removals(const bns_skeleton *sk, int32_t *depth, int64_t *sep_off,
+                                 int32_t *pool, int64_t pool_cap, int64_t *pool_len);
+
+/* Per-depth counters; up to cap entries written, *n_depths = depths run. */
+bns_status bns_skeleton_stats(const bns_skeleton *sk, bns_depth_stats *out, int32_t cap,
+                              int32_t *n_depths);
+
+void bns_skeleton_free(bns_skeleton *sk);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BNS_H */

@@ -1,0 +1,33 @@
+"""MI355X (gfx950) batched G^2 conditional-independence tests for PC-stable
+skeleton learning (Jiang, Wen, Mian, "Fast Parallel Bayesian Network Structure
+Learning").
+
+The work runs in libbns.so (HIP kernels behind the C ABI of include/bns.h);
+this package only marshals arguments.  See ``_lib`` for the entry points.
+"""
+
+from ._lib import (  # noqa: F401
+    BNS_CI_INDEPENDENT,
+    BNS_CI_RECHECKED,
+    BNS_FORM_BATCHED,
+    BNS_FORM_PLAIN,
+    BNS_PREC_FP32_RECHECK,
+    BNS_PREC_FP64,
+    EXPORTS,
+    BnsError,
+    Dataset,
+    Skeleton,
+    bns_ci_batch,
+    bns_dataset_create,
+    bns_dataset_wrap_device,
+    bns_options,
+    bns_options_default,
+    bns_pc_skeleton,
+    bns_pc_skeleton_batch,
+    bns_pc_skeleton_dataset,
+    collect,
+    free_skeleton,
+    load,
+    skeleton_batch_handles,
+    skeleton_handle,
+)

@@ -1,0 +1,95 @@
+// Internal types shared by the host driver and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bns {
+
+constexpr int kWG = 256;            // threads per workgroup (4 wave64)
+constexpr int kWaves = kWG / 64;
+constexpr int kMaxZ = 30;           // largest conditioning set a kernel accepts
+constexpr int kMaxCols = kMaxZ + 2;
+constexpr int kBinomK = kMaxZ + 1;  // binomial table columns: k = 0..kMaxZ
+constexpr int kMaxLevels = 64;      // ticket levels: level L holds test ranks [2^L - 1, 2^(L+1) - 1)
+constexpr uint32_t kMaxCells = 1u << 24;  // largest contingency table (cells)
+constexpr int kMaxDepths = 64;      // depth records kept per search
+
+// Status codes written by kernels into the control block.
+enum DevError : int32_t { kDevOk = 0, kDevTableTooLarge = 1, kDevTooManyTests = 2, kDevDepthTooLarge = 3 };
+
+// One dataset of a (possibly multi-dataset) skeleton search.
+struct ProbDev {
+    const uint8_t *data;  // column v at data + v * ld
+    int64_t ld;
+    int64_t m;
+    int32_t n;
+    int32_t var_off;      // first global variable index (cards, degree, neighbour rows)
+    int64_t adj_off;      // offset of this problem's n*n block in adjacency / pair arrays
+    double alpha;
+    int32_t max_depth;    // -1: unbounded
+    int32_t pad;
+};
+
+// One surviving edge (i < j, local ids) at the current depth.
+struct EdgeRec {
+    int32_t prob;
+    int32_t i, j;
+    int32_t posj;         // position of j in the frozen list a(i)
+    int32_t posi;         // position of i in a(j)
+    int32_t levels;       // number of ticket levels the edge takes part in
+    uint64_t nA;          // tests on side A (subsets of a(i)\{j})
+    uint64_t n;           // all tests of the edge
+};
+
+// Per-depth counters kept on the device.
+struct DepthStatDev {
+    unsigned long long edges;
+    unsigned long long required;
+    unsigned long long executed;
+    unsigned long long removed;
+    unsigned long long rechecks;
+    unsigned long long tickets;
+    double operand_bytes;
+};
+
+// Device-resident control block of a skeleton search.
+struct Ctl {
+    int32_t depth;         // depth being built / run
+    int32_t done;          // 1 once a depth has no tests (search finished)
+    int32_t error;         // DevError
+    int32_t pad0;
+    unsigned long long n_edges;        // edges in the current list
+    unsigned long long total_tickets;
+    unsigned long long ticket_ctr;
+    unsigned long long pool_used;      // sepset members written so far
+    unsigned long long level_base[kMaxLevels + 1];
+    unsigned long long level_cnt[kMaxLevels + 1];
+    unsigned int hist[kMaxLevels + 2];
+    unsigned int cursor[kMaxLevels + 2];
+    DepthStatDev stats[kMaxDepths];
+};
+
+// One CI test for the batch entry point.
+struct CiTestDev {
+    int32_t x, y, nz, zoff;
+};
+
+struct CiOutDev {
+    double g2;
+    double p;
+    int64_t df;
+    int32_t flags;
+    int32_t pad;
+};
+
+// Tunables of a launch.
+struct Tile {
+    int32_t lds_words;     // dynamic LDS per workgroup, in 32-bit words
+    int32_t max_rep_log2;  // cap on per-table replication (log2)
+    int32_t fp64;          // 1: FP64 G^2; 0: FP32 + FP64 recheck
+    int32_t pad;
+    double band;           // recheck band on |p - alpha|
+};
+
+}  // namespace bns

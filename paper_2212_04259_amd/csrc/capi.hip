@@ -1,0 +1,894 @@
+// C ABI of the gfx950 G^2 CI-test engine (include/bns.h): argument checks,
+// device-resident datasets, the batched per-depth driver of PC-stable
+// (Algorithm 1), the plain per-test driver and the CI-batch entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/bns.h"
+#include "bns_internal.h"
+#include "kernels.h"
+
+using namespace bns;
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err = "no error";
+
+static bns_status fail(bns_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            return fail(e_ == hipErrorOutOfMemory ? BNS_E_NOMEM : BNS_E_DEVICE, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                 \
+        }                                                                                  \
+    } while (0)
+
+extern "C" const char *bns_last_error(void) { return g_err.c_str(); }
+
+extern "C" void bns_options_default(bns_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->form = BNS_FORM_BATCHED;
+    o->precision = BNS_PREC_FP32_RECHECK;
+    o->recheck_band = 1e-3;
+    o->lds_bytes = 0;
+    o->wg_per_cu = 0;
+    o->use_graph = 1;
+    o->timing = 0;
+    o->stream = nullptr;
+}
+
+static bns_status read_options(const bns_options *in, bns_options *out) {
+    bns_options_default(out);
+    if (!in) return BNS_OK;
+    *out = *in;
+    if (out->form != BNS_FORM_BATCHED && out->form != BNS_FORM_PLAIN)
+        return fail(BNS_E_INVALID_ARG, "options.form must be BNS_FORM_BATCHED or BNS_FORM_PLAIN");
+    if (out->precision != BNS_PREC_FP32_RECHECK && out->precision != BNS_PREC_FP64)
+        return fail(BNS_E_INVALID_ARG, "options.precision must be a BNS_PREC_* value");
+    if (!(out->recheck_band >= 0.0) || out->recheck_band > 1.0)
+        return fail(BNS_E_INVALID_ARG, "options.recheck_band must be in [0, 1]");
+    if (out->lds_bytes < 0 || out->lds_bytes > (160 << 10))
+        return fail(BNS_E_INVALID_ARG, "options.lds_bytes must be in [0, 163840]");
+    if (out->wg_per_cu < 0 || out->wg_per_cu > 64)
+        return fail(BNS_E_INVALID_ARG, "options.wg_per_cu must be in [0, 64]");
+    for (int i = 0; i < 8; ++i)
+        if (out->reserved[i] != 0) return fail(BNS_E_INVALID_ARG, "options.reserved must be zero");
+    return BNS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Device buffers
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t ensure(size_t n) {
+        if (n <= bytes && p) return hipSuccess;
+        release();
+        size_t want = std::max<size_t>(n, 256);
+        hipError_t e = hipMalloc(&p, want);
+        if (e == hipSuccess) bytes = want;
+        return e;
+    }
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+// Per-device state: properties, a library stream, and grow-only workspaces.
+struct DevCtx {
+    int device = -1;
+    int num_cu = 0;
+    int max_lds_block = 0;
+    hipStream_t stream = nullptr;
+    std::mutex mu;
+    // skeleton search
+    DevBuf probs, var2prob, cards, binom, adj, nbr, deg, rowcnt, rowbase, edges_tmp, edges,
+        min_accept, rdepth, sepoff, pool, ctl;
+    // CI batch and plain form
+    DevBuf ci_tests, ci_z, ci_out, ci_tab, ci_taboff, plain_part, plain_ws, plain_out;
+    CiOutDev *h_out = nullptr;  // pinned readback slot
+    Ctl *h_ctl = nullptr;       // pinned control-block readback
+};
+
+static std::mutex g_ctx_mu;
+static std::vector<std::unique_ptr<DevCtx>> g_ctx;
+
+static bns_status get_ctx(int device, DevCtx **out) {
+    std::lock_guard<std::mutex> lk(g_ctx_mu);
+    for (auto &c : g_ctx)
+        if (c->device == device) {
+            *out = c.get();
+            return BNS_OK;
+        }
+    auto c = std::make_unique<DevCtx>();
+    c->device = device;
+    HIP_TRY(hipSetDevice(device));
+    HIP_TRY(hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device));
+    HIP_TRY(hipDeviceGetAttribute(&c->max_lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                  device));
+    HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    HIP_TRY(hipHostMalloc((void **)&c->h_out, sizeof(CiOutDev), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void **)&c->h_ctl, sizeof(Ctl), hipHostMallocDefault));
+    *out = c.get();
+    g_ctx.push_back(std::move(c));
+    return BNS_OK;
+}
+
+// Switches to a device for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Datasets
+// ---------------------------------------------------------------------------
+struct bns_dataset {
+    int device = -1;
+    const uint8_t *d_data = nullptr;
+    bool owns = false;
+    int64_t ld = 0;
+    int64_t m = 0;
+    int32_t n = 0;
+    std::vector<uint8_t> cards;
+    uint8_t *d_cards = nullptr;
+    ~bns_dataset() {
+        if (owns && d_data) (void)hipFree((void *)d_data);
+        if (d_cards) (void)hipFree(d_cards);
+    }
+};
+
+static bns_status check_shape(int64_t m, int32_t n, const uint8_t *cards) {
+    if (m < 1 || m > INT32_MAX) return fail(BNS_E_INVALID_ARG, "n_samples must be in [1, 2^31-1]");
+    if (n < 2 || n > 65535) return fail(BNS_E_INVALID_ARG, "n_vars must be in [2, 65535]");
+    if (!cards) return fail(BNS_E_INVALID_ARG, "cards is NULL");
+    for (int32_t v = 0; v < n; ++v)
+        if (cards[v] == 0) return fail(BNS_E_INVALID_ARG, "cards[%d] is 0", v);
+    return BNS_OK;
+}
+
+static bns_status upload_cards(bns_dataset *ds, const uint8_t *cards) {
+    ds->cards.assign(cards, cards + ds->n);
+    HIP_TRY(hipMalloc((void **)&ds->d_cards, (size_t)ds->n));
+    HIP_TRY(hipMemcpy(ds->d_cards, cards, (size_t)ds->n, hipMemcpyHostToDevice));
+    return BNS_OK;
+}
+
+extern "C" bns_status bns_dataset_create(const uint8_t *data, int64_t m, int32_t n,
+                                         const uint8_t *cards, bns_dataset **out) {
+    if (!out) return fail(BNS_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!data) return fail(BNS_E_INVALID_ARG, "data is NULL");
+    bns_status st = check_shape(m, n, cards);
+    if (st != BNS_OK) return st;
+    for (int32_t v = 0; v < n; ++v) {
+        const uint8_t *col = data + (int64_t)v * m;
+        const uint8_t r = cards[v];
+        for (int64_t s = 0; s < m; ++s)
+            if (col[s] >= r)
+                return fail(BNS_E_VALUE_RANGE, "value %u of variable %d at sample %lld >= card %u",
+                            (unsigned)col[s], v, (long long)s, (unsigned)r);
+    }
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::unique_ptr<bns_dataset> ds(new bns_dataset());
+    ds->device = dev;
+    ds->m = m;
+    ds->n = n;
+    ds->ld = (m + 255) / 256 * 256;
+    void *p = nullptr;
+    HIP_TRY(hipMalloc(&p, (size_t)ds->ld * (size_t)n));
+    ds->d_data = (const uint8_t *)p;
+    ds->owns = true;
+    HIP_TRY(hipMemset(p, 0, (size_t)ds->ld * (size_t)n));
+    HIP_TRY(hipMemcpy2D(p, (size_t)ds->ld, data, (size_t)m, (size_t)m, (size_t)n,
+                        hipMemcpyHostToDevice));
+    st = upload_cards(ds.get(), cards);
+    if (st != BNS_OK) return st;
+    *out = ds.release();
+    return BNS_OK;
+}
+
+extern "C" bns_status bns_dataset_wrap_device(const uint8_t *d_data, int64_t ld, int64_t m,
+                                              int32_t n, const uint8_t *cards, bns_dataset **out) {
+    if (!out) return fail(BNS_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!d_data) return fail(BNS_E_INVALID_ARG, "d_data is NULL");
+    bns_status st = check_shape(m, n, cards);
+    if (st != BNS_OK) return st;
+    if (ld < m || (ld % 16) != 0) return fail(BNS_E_INVALID_ARG, "ld must be >= n_samples and a multiple of 16");
+    if (((uintptr_t)d_data % 16) != 0) return fail(BNS_E_INVALID_ARG, "d_data must be 16-byte aligned");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::unique_ptr<bns_dataset> ds(new bns_dataset());
+    ds->device = dev;
+    ds->m = m;
+    ds->n = n;
+    ds->ld = ld;
+    ds->d_data = d_data;
+    ds->owns = false;
+    st = upload_cards(ds.get(), cards);
+    if (st != BNS_OK) return st;
+    DevCtx *dc = nullptr;
+    st = get_ctx(dev, &dc);
+    if (st != BNS_OK) return st;
+    std::lock_guard<std::mutex> lk(dc->mu);
+    unsigned long long *bad = nullptr;
+    HIP_TRY(hipMalloc((void **)&bad, sizeof(unsigned long long)));
+    const unsigned long long init = ~0ull;
+    unsigned long long hbad = ~0ull;
+    hipError_t e = hipMemcpy(bad, &init, sizeof(init), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_validate(d_data, ld, m, n, ds->d_cards, bad, dc->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, dc->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(dc->stream);
+    (void)hipFree(bad);
+    HIP_TRY(e);
+    if (hbad != ~0ull) {
+        const int64_t v = (int64_t)(hbad / (unsigned long long)m), s = (int64_t)(hbad % (unsigned long long)m);
+        return fail(BNS_E_VALUE_RANGE, "value of variable %lld at sample %lld >= card %u", (long long)v,
+                    (long long)s, (unsigned)cards[v]);
+    }
+    *out = ds.release();
+    return BNS_OK;
+}
+
+extern "C" void bns_dataset_free(bns_dataset *ds) { delete ds; }
+
+// ---------------------------------------------------------------------------
+// Tiles
+// ---------------------------------------------------------------------------
+static const int kDefaultLdsBytes = 48 << 10;
+
+static bns_status make_tile(const DevCtx &dc, const bns_options &o, Tile *t) {
+    int lds = o.lds_bytes ? o.lds_bytes : kDefaultLdsBytes;
+    const int static_reserve = 4096;  // TestSh + TicketSh + reductions
+    if (lds + static_reserve > dc.max_lds_block) lds = dc.max_lds_block - static_reserve;
+    lds &= ~255;
+    if (lds < 4096) return fail(BNS_E_DEVICE, "device LDS per workgroup too small (%d bytes)", dc.max_lds_block);
+    if (lds > (64 << 10) - static_reserve) {
+        hipError_t e = allow_dynamic_lds(lds);
+        if (e != hipSuccess) return fail(BNS_E_DEVICE, "cannot enable %d bytes of dynamic LDS: %s", lds, hipGetErrorString(e));
+    }
+    t->lds_words = lds / 4;
+    t->max_rep_log2 = 6;
+    t->fp64 = (o.precision == BNS_PREC_FP64) ? 1 : 0;
+    t->band = o.recheck_band;
+    t->pad = 0;
+    return BNS_OK;
+}
+
+static bns_status check_table(const std::vector<uint8_t> &cards, int x, int y, const int32_t *z,
+                              int nz, const Tile &tile) {
+    uint64_t rxy = (uint64_t)cards[x] * cards[y];
+    uint64_t T = rxy;
+    for (int k = 0; k < nz; ++k) {
+        T *= cards[z[k]];
+        if (T > kMaxCells) return fail(BNS_E_TABLE_TOO_LARGE, "table of test %d-%d exceeds %u cells", x, y, kMaxCells);
+    }
+    if (rxy + cards[x] + cards[y] + 1 > (uint64_t)tile.lds_words)
+        return fail(BNS_E_TABLE_TOO_LARGE, "r_x * r_y of test %d-%d exceeds the LDS budget", x, y);
+    return BNS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// bns_ci_batch
+// ---------------------------------------------------------------------------
+extern "C" bns_status bns_ci_batch(const bns_dataset *ds, const bns_ci_test *tests, int64_t n_tests,
+                                   const int32_t *z_pool, int64_t z_pool_len, double alpha,
+                                   const bns_options *opt, double *g2, int64_t *df, double *p,
+                                   int32_t *flags, int32_t *tables_out,
+                                   const int64_t *table_offsets) {
+    if (!ds) return fail(BNS_E_INVALID_ARG, "dataset is NULL");
+    if (n_tests < 0) return fail(BNS_E_INVALID_ARG, "n_tests < 0");
+    if (n_tests > 0 && !tests) return fail(BNS_E_INVALID_ARG, "tests is NULL");
+    if (z_pool_len < 0 || (z_pool_len > 0 && !z_pool)) return fail(BNS_E_INVALID_ARG, "bad z_pool");
+    if (!(alpha > 0.0 && alpha < 1.0)) return fail(BNS_E_INVALID_ARG, "alpha must be in (0, 1)");
+    if (tables_out && !table_offsets) return fail(BNS_E_INVALID_ARG, "tables_out needs table_offsets");
+    bns_options o;
+    bns_status st = read_options(opt, &o);
+    if (st != BNS_OK) return st;
+    if (n_tests == 0) return BNS_OK;
+    DevCtx *dc = nullptr;
+    st = get_ctx(ds->device, &dc);
+    if (st != BNS_OK) return st;
+    Tile tile;
+    st = make_tile(*dc, o, &tile);
+    if (st != BNS_OK) return st;
+    const int n = ds->n;
+    for (int64_t t = 0; t < n_tests; ++t) {
+        const bns_ci_test &q = tests[t];
+        if (q.x < 0 || q.x >= n || q.y < 0 || q.y >= n || q.x == q.y)
+            return fail(BNS_E_INVALID_ARG, "test %lld: bad x/y", (long long)t);
+        if (q.n_z < 0 || q.n_z > kMaxZ) return fail(BNS_E_INVALID_ARG, "test %lld: n_z out of [0, %d]", (long long)t, kMaxZ);
+        if (q.n_z > 0 && (q.z_offset < 0 || (int64_t)q.z_offset + q.n_z > z_pool_len))
+            return fail(BNS_E_INVALID_ARG, "test %lld: z range outside z_pool", (long long)t);
+        for (int k = 0; k < q.n_z; ++k) {
+            const int32_t zv = z_pool[q.z_offset + k];
+            if (zv < 0 || zv >= n || zv == q.x || zv == q.y)
+                return fail(BNS_E_INVALID_ARG, "test %lld: bad conditioning variable %d", (long long)t, zv);
+        }
+        st = check_table(ds->cards, q.x, q.y, q.n_z ? z_pool + q.z_offset : nullptr, q.n_z, tile);
+        if (st != BNS_OK) return st;
+    }
+    DeviceGuard dg(ds->device);
+    if (!dg.ok) return fail(BNS_E_DEVICE, "cannot select device %d", ds->device);
+    std::lock_guard<std::mutex> lk(dc->mu);
+    hipStream_t s = o.stream ? (hipStream_t)o.stream : dc->stream;
+    HIP_TRY(dc->ci_tests.ensure(sizeof(CiTestDev) * (size_t)n_tests));
+    HIP_TRY(dc->ci_z.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(z_pool_len, 1)));
+    HIP_TRY(dc->ci_out.ensure(sizeof(CiOutDev) * (size_t)n_tests));
+    std::vector<CiTestDev> ht((size_t)n_tests);
+    int64_t tab_total = 0;
+    for (int64_t t = 0; t < n_tests; ++t) {
+        ht[t] = {tests[t].x, tests[t].y, tests[t].n_z, tests[t].z_offset};
+        if (tables_out) {
+            int64_t T = (int64_t)ds->cards[tests[t].x] * ds->cards[tests[t].y];
+            for (int k = 0; k < tests[t].n_z; ++k) T *= ds->cards[z_pool[tests[t].z_offset + k]];
+            if (table_offsets[t] < 0) return fail(BNS_E_INVALID_ARG, "negative table offset");
+            tab_total = std::max(tab_total, table_offsets[t] + T);
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(dc->ci_tests.p, ht.data(), sizeof(CiTestDev) * (size_t)n_tests,
+                           hipMemcpyHostToDevice, s));
+    if (z_pool_len > 0)
+        HIP_TRY(hipMemcpyAsync(dc->ci_z.p, z_pool, sizeof(int32_t) * (size_t)z_pool_len,
+                               hipMemcpyHostToDevice, s));
+    uint32_t *d_tab = nullptr;
+    const int64_t *d_taboff = nullptr;
+    if (tables_out) {
+        HIP_TRY(dc->ci_tab.ensure(sizeof(uint32_t) * (size_t)tab_total));
+        HIP_TRY(dc->ci_taboff.ensure(sizeof(int64_t) * (size_t)n_tests));
+        HIP_TRY(hipMemcpyAsync(dc->ci_taboff.p, table_offsets, sizeof(int64_t) * (size_t)n_tests,
+                               hipMemcpyHostToDevice, s));
+        d_tab = dc->ci_tab.as<uint32_t>();
+        d_taboff = dc->ci_taboff.as<int64_t>();
+    }
+    const int wg = std::max(1, depth_tests_max_wg_per_cu(tile.lds_words * 4));
+    const int grid = (int)std::min<int64_t>(n_tests, (int64_t)dc->num_cu * wg);
+    HIP_TRY(launch_ci_batch(ds->d_data, ds->ld, ds->m, ds->d_cards, dc->ci_tests.as<CiTestDev>(),
+                            dc->ci_z.as<int32_t>(), n_tests, alpha, tile, dc->ci_out.as<CiOutDev>(),
+                            d_tab, d_taboff, grid, s));
+    std::vector<CiOutDev> ho((size_t)n_tests);
+    HIP_TRY(hipMemcpyAsync(ho.data(), dc->ci_out.p, sizeof(CiOutDev) * (size_t)n_tests,
+                           hipMemcpyDeviceToHost, s));
+    if (tables_out)
+        HIP_TRY(hipMemcpyAsync(tables_out, d_tab, sizeof(uint32_t) * (size_t)tab_total,
+                               hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int64_t t = 0; t < n_tests; ++t) {
+        if (ho[t].flags >> 8) return fail(BNS_E_TABLE_TOO_LARGE, "test %lld exceeded device limits", (long long)t);
+        if (g2) g2[t] = ho[t].g2;
+        if (df) df[t] = ho[t].df;
+        if (p) p[t] = ho[t].p;
+        if (flags) flags[t] = ho[t].flags & 3;
+    }
+    return BNS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Skeleton results
+// ---------------------------------------------------------------------------
+struct bns_skeleton {
+    int32_t n = 0;
+    std::vector<uint8_t> adj;
+    std::vector<int32_t> depth;
+    std::vector<int64_t> sepoff;
+    std::vector<int32_t> pool;
+    std::vector<bns_depth_stats> stats;
+};
+
+extern "C" int32_t bns_skeleton_n_vars(const bns_skeleton *sk) { return sk ? sk->n : 0; }
+
+extern "C" bns_status bns_skeleton_adjacency(const bns_skeleton *sk, uint8_t *adj) {
+    if (!sk || !adj) return fail(BNS_E_INVALID_ARG, "NULL argument");
+    std::memcpy(adj, sk->adj.data(), sk->adj.size());
+    return BNS_OK;
+}
+
+extern "C" bns_status bns_skeleton_sepset(const bns_skeleton *sk, int32_t i, int32_t j,
+                                          int32_t *members, int32_t cap, int32_t *len,
+                                          int32_t *removal_depth) {
+    if (!sk || !len) return fail(BNS_E_INVALID_ARG, "NULL argument");
+    if (i < 0 || j < 0 || i >= sk->n || j >= sk->n || i == j) return fail(BNS_E_INVALID_ARG, "bad pair");
+    if (cap < 0 || (cap > 0 && !members)) return fail(BNS_E_INVALID_ARG, "bad members buffer");
+    const int64_t ij = (int64_t)i * sk->n + j;
+    const int32_t d = sk->depth[ij];
+    if (removal_depth) *removal_depth = d;
+    if (d < 0) {
+        *len = -1;
+        return BNS_OK;
+    }
+    *len = d;
+    const int64_t off = sk->sepoff[ij];
+    for (int32_t k = 0; k < d && k < cap; ++k) members[k] = sk->pool[off + k];
+    return BNS_OK;
+}
+
+extern "C" bns_status bns_skeleton_removals(const bns_skeleton *sk, int32_t *depth, int64_t *sep_off,
+                                            int32_t *pool, int64_t pool_cap, int64_t *pool_len) {
+    if (!sk) return fail(BNS_E_INVALID_ARG, "NULL skeleton");
+    if (pool_cap < 0 || (pool_cap > 0 && !pool)) return fail(BNS_E_INVALID_ARG, "bad pool buffer");
+    if (depth) std::memcpy(depth, sk->depth.data(), sk->depth.size() * sizeof(int32_t));
+    if (sep_off) std::memcpy(sep_off, sk->sepoff.data(), sk->sepoff.size() * sizeof(int64_t));
+    if (pool) std::memcpy(pool, sk->pool.data(), sizeof(int32_t) * (size_t)std::min<int64_t>(pool_cap, (int64_t)sk->pool.size()));
+    if (pool_len) *pool_len = (int64_t)sk->pool.size();
+    return BNS_OK;
+}
+
+extern "C" bns_status bns_skeleton_stats(const bns_skeleton *sk, bns_depth_stats *out, int32_t cap,
+                                         int32_t *n_depths) {
+    if (!sk || !n_depths) return fail(BNS_E_INVALID_ARG, "NULL argument");
+    if (cap < 0 || (cap > 0 && !out)) return fail(BNS_E_INVALID_ARG, "bad stats buffer");
+    *n_depths = (int32_t)sk->stats.size();
+    for (int32_t d = 0; d < cap && d < (int32_t)sk->stats.size(); ++d) out[d] = sk->stats[d];
+    return BNS_OK;
+}
+
+extern "C" void bns_skeleton_free(bns_skeleton *sk) { delete sk; }
+
+// ---------------------------------------------------------------------------
+// Batched form: device-resident queue, one persistent test launch per depth.
+// ---------------------------------------------------------------------------
+static void build_binom(int rows, std::vector<uint64_t> &B) {
+    const uint64_t sat = ~0ull >> 2;
+    B.assign((size_t)rows * kBinomK, 0);
+    for (int n = 0; n < rows; ++n) {
+        B[(size_t)n * kBinomK] = 1;
+        for (int k = 1; k < kBinomK && k <= n; ++k) {
+            const uint64_t a = B[(size_t)(n - 1) * kBinomK + k - 1];
+            const uint64_t b = (k <= n - 1) ? B[(size_t)(n - 1) * kBinomK + k] : 0;
+            B[(size_t)n * kBinomK + k] = (a >= sat || b >= sat || a + b >= sat) ? sat : a + b;
+        }
+    }
+}
+
+static bns_status dev_error(int32_t e) {
+    switch (e) {
+        case kDevTableTooLarge: return fail(BNS_E_TABLE_TOO_LARGE, "a test's contingency table exceeds the supported size");
+        case kDevTooManyTests: return fail(BNS_E_TABLE_TOO_LARGE, "an edge has more conditioning sets than supported");
+        case kDevDepthTooLarge: return fail(BNS_E_TABLE_TOO_LARGE, "the search exceeds the supported depth");
+        default: return fail(BNS_E_INTERNAL, "device error %d", e);
+    }
+}
+
+struct Graph {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    ~Graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t P,
+                              const double *alpha, const int32_t *maxd, const bns_options &o,
+                              std::vector<bns_skeleton *> &outs) {
+    Tile tile;
+    bns_status st = make_tile(dc, o, &tile);
+    if (st != BNS_OK) return st;
+    hipStream_t s = o.stream ? (hipStream_t)o.stream : dc.stream;
+
+    std::vector<ProbDev> probs((size_t)P);
+    std::vector<int32_t> var2prob;
+    std::vector<uint8_t> gcards;
+    int64_t adj_total = 0, pairs_total = 0;
+    int32_t G = 0, nmax = 0, dmax = -1;
+    bool unbounded = false;
+    for (int32_t k = 0; k < P; ++k) {
+        const bns_dataset *d = ds[k];
+        probs[k] = {d->d_data, d->ld, d->m, d->n, G, adj_total, alpha[k], maxd[k], 0};
+        for (int32_t v = 0; v < d->n; ++v) var2prob.push_back(k);
+        gcards.insert(gcards.end(), d->cards.begin(), d->cards.end());
+        G += d->n;
+        adj_total += (int64_t)d->n * d->n;
+        pairs_total += (int64_t)d->n * (d->n - 1) / 2;
+        nmax = std::max(nmax, d->n);
+        if (maxd[k] < 0) unbounded = true;
+        dmax = std::max(dmax, maxd[k]);
+    }
+    std::vector<uint64_t> B;
+    const int brows = nmax + 1;
+    build_binom(brows, B);
+
+    HIP_TRY(dc.probs.ensure(sizeof(ProbDev) * (size_t)P));
+    HIP_TRY(dc.var2prob.ensure(sizeof(int32_t) * (size_t)G));
+    HIP_TRY(dc.cards.ensure((size_t)G));
+    HIP_TRY(dc.binom.ensure(sizeof(uint64_t) * B.size()));
+    HIP_TRY(dc.adj.ensure((size_t)adj_total));
+    HIP_TRY(dc.nbr.ensure(sizeof(int32_t) * (size_t)adj_total));
+    HIP_TRY(dc.rdepth.ensure(sizeof(int32_t) * (size_t)adj_total));
+    HIP_TRY(dc.sepoff.ensure(sizeof(int64_t) * (size_t)adj_total));
+    HIP_TRY(dc.deg.ensure(sizeof(int32_t) * (size_t)G));
+    HIP_TRY(dc.rowcnt.ensure(sizeof(int32_t) * (size_t)G));
+    HIP_TRY(dc.rowbase.ensure(sizeof(int64_t) * (size_t)G));
+    HIP_TRY(dc.edges_tmp.ensure(sizeof(EdgeRec) * (size_t)pairs_total));
+    HIP_TRY(dc.edges.ensure(sizeof(EdgeRec) * (size_t)pairs_total));
+    HIP_TRY(dc.min_accept.ensure(sizeof(unsigned long long) * (size_t)pairs_total));
+    HIP_TRY(dc.ctl.ensure(sizeof(Ctl)));
+    HIP_TRY(dc.pool.ensure(sizeof(int32_t) * 1024));
+    HIP_TRY(hipMemcpyAsync(dc.probs.p, probs.data(), sizeof(ProbDev) * (size_t)P, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dc.var2prob.p, var2prob.data(), sizeof(int32_t) * (size_t)G, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dc.cards.p, gcards.data(), (size_t)G, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dc.binom.p, B.data(), sizeof(uint64_t) * B.size(), hipMemcpyHostToDevice, s));
+
+    DepthArgs a;
+    a.probs = dc.probs.as<ProbDev>();
+    a.n_probs = P;
+    a.n_globals = G;
+    a.var2prob = dc.var2prob.as<int32_t>();
+    a.cards = dc.cards.as<uint8_t>();
+    a.binom = dc.binom.as<uint64_t>();
+    a.binom_rows = brows;
+    a.pad = 0;
+    a.adj = dc.adj.as<uint8_t>();
+    a.nbr = dc.nbr.as<int32_t>();
+    a.deg = dc.deg.as<int32_t>();
+    a.rowcnt = dc.rowcnt.as<int32_t>();
+    a.rowbase = dc.rowbase.as<int64_t>();
+    a.edges_tmp = dc.edges_tmp.as<EdgeRec>();
+    a.edges = dc.edges.as<EdgeRec>();
+    a.min_accept = dc.min_accept.as<unsigned long long>();
+    a.rdepth = dc.rdepth.as<int32_t>();
+    a.sepoff = dc.sepoff.as<int64_t>();
+    a.pool = dc.pool.as<int32_t>();
+    a.ctl = dc.ctl.as<Ctl>();
+    a.tile = tile;
+
+    const int lds_bytes = tile.lds_words * 4;
+    int wg = o.wg_per_cu ? o.wg_per_cu : depth_tests_max_wg_per_cu(lds_bytes);
+    const int grid = std::max(1, dc.num_cu * wg);
+
+    HIP_TRY(launch_init_search(a, s));
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (o.timing) {
+        HIP_TRY(hipEventCreate(&ev0));
+        HIP_TRY(hipEventCreate(&ev1));
+    }
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } evg{ev0, ev1};
+
+    std::unique_ptr<Graph> graph;
+    int32_t* graph_pool = nullptr;
+    const bool use_graph = o.use_graph && !o.timing;
+
+    std::vector<bns_depth_stats> stats;
+    unsigned long long alive = (unsigned long long)pairs_total;  // edges alive at the next depth
+    unsigned long long pool_used = 0;
+    for (int d = 0;; ++d) {
+        if (!unbounded && d > dmax) break;
+        if (d >= kMaxDepths) return fail(BNS_E_TABLE_TOO_LARGE, "the search exceeds %d depths", kMaxDepths);
+        // Sepset slots for every edge that may be removed at this depth.
+        const size_t need = (size_t)(pool_used + alive * (unsigned long long)d);
+        if (need > dc.pool.bytes / sizeof(int32_t)) {
+            DevBuf nb;
+            HIP_TRY(nb.ensure(sizeof(int32_t) * std::max(need, 2 * dc.pool.bytes / sizeof(int32_t))));
+            if (pool_used)
+                HIP_TRY(hipMemcpyAsync(nb.p, dc.pool.p, sizeof(int32_t) * (size_t)pool_used, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            std::swap(dc.pool.p, nb.p);
+            std::swap(dc.pool.bytes, nb.bytes);
+            a.pool = dc.pool.as<int32_t>();
+        }
+        if (use_graph) {
+            if (!graph || graph_pool != a.pool) {
+                graph.reset(new Graph());
+                HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                hipError_t e1 = launch_depth_prepare(a, s);
+                hipError_t e2 = launch_depth_tests(a, grid, s);
+                hipError_t e3 = launch_depth_apply(a, s);
+                hipError_t e4 = hipStreamEndCapture(s, &graph->graph);
+                HIP_TRY(e1);
+                HIP_TRY(e2);
+                HIP_TRY(e3);
+                HIP_TRY(e4);
+                HIP_TRY(hipGraphInstantiate(&graph->exec, graph->graph, nullptr, nullptr, 0));
+                graph_pool = a.pool;
+            }
+            HIP_TRY(hipGraphLaunch(graph->exec, s));
+        } else {
+            HIP_TRY(launch_depth_prepare(a, s));
+            if (o.timing) HIP_TRY(hipEventRecord(ev0, s));
+            HIP_TRY(launch_depth_tests(a, grid, s));
+            if (o.timing) HIP_TRY(hipEventRecord(ev1, s));
+            HIP_TRY(launch_depth_apply(a, s));
+        }
+        HIP_TRY(hipMemcpyAsync(dc.h_ctl, dc.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const Ctl &c = *dc.h_ctl;
+        if (c.error) return dev_error(c.error);
+        if (c.done) break;
+        const DepthStatDev &sd = c.stats[d];
+        bns_depth_stats r;
+        std::memset(&r, 0, sizeof(r));
+        r.depth = d;
+        r.edges = (int64_t)sd.edges;
+        r.tests_required = (int64_t)sd.required;
+        r.tests_executed = (int64_t)sd.executed;
+        r.removed = (int64_t)sd.removed;
+        r.rechecks = (int64_t)sd.rechecks;
+        r.tickets = (int64_t)sd.tickets;
+        r.operand_bytes = sd.operand_bytes;
+        if (o.timing) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
+            r.kernel_seconds = ms * 1e-3;
+        }
+        stats.push_back(r);
+        alive = sd.edges - sd.removed;
+        pool_used = c.pool_used;
+    }
+
+    // Results: adjacency, removal depths, sepset offsets and members.
+    std::vector<uint8_t> hadj((size_t)adj_total);
+    std::vector<int32_t> hdep((size_t)adj_total);
+    std::vector<int64_t> hoff((size_t)adj_total);
+    std::vector<int32_t> hpool((size_t)std::max<unsigned long long>(pool_used, 1));
+    HIP_TRY(hipMemcpyAsync(hadj.data(), dc.adj.p, hadj.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hdep.data(), dc.rdepth.p, hdep.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hoff.data(), dc.sepoff.p, hoff.size() * 8, hipMemcpyDeviceToHost, s));
+    if (pool_used)
+        HIP_TRY(hipMemcpyAsync(hpool.data(), dc.pool.p, (size_t)pool_used * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int32_t k = 0; k < P; ++k) {
+        std::unique_ptr<bns_skeleton> sk(new bns_skeleton());
+        const int n = ds[k]->n;
+        const int64_t base = probs[k].adj_off, nn = (int64_t)n * n;
+        sk->n = n;
+        sk->adj.assign(hadj.begin() + base, hadj.begin() + base + nn);
+        sk->depth.assign(hdep.begin() + base, hdep.begin() + base + nn);
+        sk->sepoff.assign((size_t)nn, -1);
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) {
+                const int64_t ij = (int64_t)i * n + j, ji = (int64_t)j * n + i;
+                const int32_t dd = sk->depth[ij];
+                if (dd < 0) continue;
+                const int64_t src = hoff[base + ij];
+                sk->sepoff[ij] = sk->sepoff[ji] = (int64_t)sk->pool.size();
+                for (int q = 0; q < dd; ++q) sk->pool.push_back(hpool[src + q]);
+            }
+        sk->stats = stats;
+        outs[k] = sk.release();
+    }
+    return BNS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Plain form: the host walks the tests in the sequential order; every test is
+// one sample-parallel counting launch plus a finishing launch and a readback.
+// ---------------------------------------------------------------------------
+static bns_status plain_test(DevCtx &dc, const bns_dataset *ds, const Tile &tile, hipStream_t s,
+                             const int32_t *vars, int ncols, double alpha, CiOutDev *res) {
+    PlainTest pt;
+    std::memset(&pt, 0, sizeof(pt));
+    pt.ncols = ncols;
+    int64_t T = 1, Z = 1;
+    for (int k = 0; k < ncols; ++k) {
+        pt.vars[k] = vars[k];
+        T *= ds->cards[vars[k]];
+        if (k >= 2) Z *= ds->cards[vars[k]];
+        if (T > (int64_t)kMaxCells) return fail(BNS_E_TABLE_TOO_LARGE, "table exceeds %u cells", kMaxCells);
+    }
+    const int64_t spb = 4096;
+    const int nblocks = (int)std::max<int64_t>(1, (ds->m + spb - 1) / spb);
+    HIP_TRY(dc.plain_part.ensure(sizeof(uint32_t) * (size_t)T * (size_t)nblocks));
+    const int64_t ws = T + (int64_t)(ds->cards[vars[0]] + ds->cards[vars[1]] + 1) * Z;
+    HIP_TRY(dc.plain_ws.ensure(sizeof(uint32_t) * (size_t)ws));
+    HIP_TRY(dc.plain_out.ensure(sizeof(CiOutDev)));
+    HIP_TRY(launch_plain_count(ds->d_data, ds->ld, ds->m, ds->d_cards, pt, spb, nblocks,
+                               dc.plain_part.as<uint32_t>(), T, tile.lds_words, s));
+    HIP_TRY(launch_plain_finish(ds->d_cards, pt, nblocks, dc.plain_part.as<uint32_t>(), T,
+                                dc.plain_ws.as<uint32_t>(), alpha, dc.plain_out.as<CiOutDev>(), s));
+    HIP_TRY(hipMemcpyAsync(dc.h_out, dc.plain_out.p, sizeof(CiOutDev), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *res = *dc.h_out;
+    return BNS_OK;
+}
+
+static bool next_subset(std::vector<int32_t> &idx, int d, int p) {
+    int k = d - 1;
+    while (k >= 0 && idx[k] == p - d + k) --k;
+    if (k < 0) return false;
+    ++idx[k];
+    for (int l = k + 1; l < d; ++l) idx[l] = idx[l - 1] + 1;
+    return true;
+}
+
+static bns_status run_plain(DevCtx &dc, const bns_dataset *ds, double alpha, int32_t max_depth,
+                            const bns_options &o, bns_skeleton **out) {
+    Tile tile;
+    bns_status st = make_tile(dc, o, &tile);
+    if (st != BNS_OK) return st;
+    hipStream_t s = o.stream ? (hipStream_t)o.stream : dc.stream;
+    const int n = ds->n;
+    std::unique_ptr<bns_skeleton> sk(new bns_skeleton());
+    sk->n = n;
+    sk->adj.assign((size_t)n * n, 0);
+    sk->depth.assign((size_t)n * n, -1);
+    sk->sepoff.assign((size_t)n * n, -1);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) sk->adj[(size_t)i * n + j] = (i != j);
+    std::vector<std::vector<int32_t>> a((size_t)n);
+    std::vector<int32_t> vars(kMaxCols), candA, candB, idx;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (o.timing) {
+        HIP_TRY(hipEventCreate(&ev0));
+        HIP_TRY(hipEventCreate(&ev1));
+    }
+    for (int d = 0; max_depth < 0 || d <= max_depth; ++d) {
+        if (d >= kMaxDepths) return fail(BNS_E_TABLE_TOO_LARGE, "the search exceeds %d depths", kMaxDepths);
+        for (int v = 0; v < n; ++v) {
+            a[v].clear();
+            for (int u = 0; u < n; ++u)
+                if (sk->adj[(size_t)v * n + u]) a[v].push_back(u);
+        }
+        bool any = false;
+        for (int i = 0; i < n && !any; ++i)
+            for (int j = i + 1; j < n; ++j)
+                if (sk->adj[(size_t)i * n + j] && (d == 0 || (int)a[i].size() - 1 >= d || (int)a[j].size() - 1 >= d)) {
+                    any = true;
+                    break;
+                }
+        if (!any) break;
+        if (d > kMaxZ) return fail(BNS_E_TABLE_TOO_LARGE, "the search exceeds depth %d", kMaxZ);
+        bns_depth_stats r;
+        std::memset(&r, 0, sizeof(r));
+        r.depth = d;
+        if (o.timing) HIP_TRY(hipEventRecord(ev0, s));
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) {
+                if (!sk->adj[(size_t)i * n + j]) continue;
+                ++r.edges;
+                vars[0] = i;
+                vars[1] = j;
+                bool removed = false;
+                for (int side = 0; side < 2 && !removed; ++side) {
+                    if (d == 0 && side == 1) break;
+                    std::vector<int32_t> &cand = side == 0 ? candA : candB;
+                    cand.clear();
+                    const int owner = side == 0 ? i : j, other = side == 0 ? j : i;
+                    for (int u : a[owner])
+                        if (u != other) cand.push_back(u);
+                    const int p = (int)cand.size();
+                    if (p < d) continue;
+                    idx.resize((size_t)d);
+                    for (int k = 0; k < d; ++k) idx[k] = k;
+                    do {
+                        for (int k = 0; k < d; ++k) vars[2 + k] = cand[idx[k]];
+                        CiOutDev res;
+                        st = plain_test(dc, ds, tile, s, vars.data(), d + 2, alpha, &res);
+                        if (st != BNS_OK) return st;
+                        ++r.tests_required;
+                        ++r.tests_executed;
+                        r.operand_bytes += (double)(d + 2) * (double)ds->m;
+                        if (res.p > alpha) {
+                            const size_t ij = (size_t)i * n + j, ji = (size_t)j * n + i;
+                            sk->adj[ij] = sk->adj[ji] = 0;
+                            sk->depth[ij] = sk->depth[ji] = d;
+                            sk->sepoff[ij] = sk->sepoff[ji] = (int64_t)sk->pool.size();
+                            for (int k = 0; k < d; ++k) sk->pool.push_back(vars[2 + k]);
+                            ++r.removed;
+                            removed = true;
+                            break;
+                        }
+                    } while (d > 0 && next_subset(idx, d, p));
+                }
+            }
+        if (o.timing) {
+            HIP_TRY(hipEventRecord(ev1, s));
+            HIP_TRY(hipEventSynchronize(ev1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
+            r.kernel_seconds = ms * 1e-3;
+        }
+        sk->stats.push_back(r);
+    }
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    *out = sk.release();
+    return BNS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Skeleton entry points
+// ---------------------------------------------------------------------------
+extern "C" bns_status bns_pc_skeleton_batch(const bns_dataset *const *ds, int32_t n_problems,
+                                            const double *alpha, const int32_t *max_depth,
+                                            const bns_options *opt, bns_skeleton **outs) {
+    if (!ds || !alpha || !max_depth || !outs || n_problems < 1)
+        return fail(BNS_E_INVALID_ARG, "NULL argument or n_problems < 1");
+    for (int32_t k = 0; k < n_problems; ++k) outs[k] = nullptr;
+    bns_options o;
+    bns_status st = read_options(opt, &o);
+    if (st != BNS_OK) return st;
+    int64_t pairs = 0;
+    for (int32_t k = 0; k < n_problems; ++k) {
+        if (!ds[k]) return fail(BNS_E_INVALID_ARG, "dataset %d is NULL", k);
+        if (!(alpha[k] > 0.0 && alpha[k] < 1.0)) return fail(BNS_E_INVALID_ARG, "alpha[%d] must be in (0, 1)", k);
+        if (max_depth[k] < -1) return fail(BNS_E_INVALID_ARG, "max_depth[%d] must be >= -1", k);
+        if (ds[k]->device != ds[0]->device) return fail(BNS_E_INVALID_ARG, "datasets on different devices");
+        pairs += (int64_t)ds[k]->n * (ds[k]->n - 1) / 2;
+    }
+    if (pairs > (int64_t)UINT32_MAX) return fail(BNS_E_INVALID_ARG, "too many variable pairs in one batch");
+    if (o.form == BNS_FORM_PLAIN && n_problems != 1)
+        return fail(BNS_E_INVALID_ARG, "the plain form runs one dataset at a time");
+    DevCtx *dc = nullptr;
+    st = get_ctx(ds[0]->device, &dc);
+    if (st != BNS_OK) return st;
+    DeviceGuard dg(ds[0]->device);
+    if (!dg.ok) return fail(BNS_E_DEVICE, "cannot select device %d", ds[0]->device);
+    std::lock_guard<std::mutex> lk(dc->mu);
+    if (o.form == BNS_FORM_PLAIN) return run_plain(*dc, ds[0], alpha[0], max_depth[0], o, outs);
+    std::vector<bns_skeleton *> res((size_t)n_problems, nullptr);
+    st = run_batched(*dc, ds, n_problems, alpha, max_depth, o, res);
+    if (st != BNS_OK) {
+        for (auto *r : res) delete r;
+        return st;
+    }
+    for (int32_t k = 0; k < n_problems; ++k) outs[k] = res[k];
+    return BNS_OK;
+}
+
+extern "C" bns_status bns_pc_skeleton_dataset(const bns_dataset *ds, double alpha, int32_t max_depth,
+                                              const bns_options *opt, bns_skeleton **out) {
+    if (!out) return fail(BNS_E_INVALID_ARG, "out is NULL");
+    return bns_pc_skeleton_batch(&ds, 1, &alpha, &max_depth, opt, out);
+}
+
+extern "C" bns_status bns_pc_skeleton(const uint8_t *data, int64_t n_samples, int32_t n_vars,
+                                      const uint8_t *cards, double alpha, int32_t max_depth,
+                                      const bns_options *opt, bns_skeleton **out) {
+    if (!out) return fail(BNS_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!(alpha > 0.0 && alpha < 1.0)) return fail(BNS_E_INVALID_ARG, "alpha must be in (0, 1)");
+    if (max_depth < -1) return fail(BNS_E_INVALID_ARG, "max_depth must be >= -1");
+    bns_options o;
+    bns_status st = read_options(opt, &o);
+    if (st != BNS_OK) return st;
+    bns_dataset *ds = nullptr;
+    st = bns_dataset_create(data, n_samples, n_vars, cards, &ds);
+    if (st != BNS_OK) return st;
+    st = bns_pc_skeleton_dataset(ds, alpha, max_depth, &o, out);
+    bns_dataset_free(ds);
+    return st;
+}

@@ -1,0 +1,68 @@
+// Host-side launchers of the gfx950 kernels (defined in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bns_internal.h"
+
+namespace bns {
+
+// Arguments of the per-depth pipeline of a skeleton search (all device pointers).
+struct DepthArgs {
+    const ProbDev *probs;
+    int32_t n_probs;
+    int32_t n_globals;        // sum of n over problems
+    const int32_t *var2prob;  // global variable -> problem
+    const uint8_t *cards;     // per global variable
+    const uint64_t *binom;    // binom[n * kBinomK + k], saturated
+    int32_t binom_rows;
+    int32_t pad;
+    uint8_t *adj;             // per problem n*n block at adj_off
+    int32_t *nbr;             // frozen adjacency lists, same blocks as adj
+    int32_t *deg;             // per global variable
+    int32_t *rowcnt;          // per global variable: alive edges (v, u > v)
+    int64_t *rowbase;         // exclusive scan of rowcnt
+    EdgeRec *edges_tmp;
+    EdgeRec *edges;           // sorted by levels, descending
+    unsigned long long *min_accept;
+    int32_t *rdepth;          // per pair (problem block), removal depth or -1
+    int64_t *sepoff;          // per pair, offset in pool or -1
+    int32_t *pool;            // sepset members
+    Ctl *ctl;
+    Tile tile;
+};
+
+hipError_t launch_depth_prepare(const DepthArgs &a, hipStream_t s);   // snapshot .. scatter
+hipError_t launch_depth_tests(const DepthArgs &a, int grid, hipStream_t s);
+hipError_t launch_depth_apply(const DepthArgs &a, hipStream_t s);     // removals + finalize
+hipError_t launch_init_search(const DepthArgs &a, hipStream_t s);     // complete graph, reset
+int depth_tests_max_wg_per_cu(int lds_bytes);
+hipError_t allow_dynamic_lds(int bytes);  // raises the per-kernel dynamic LDS limit
+
+// Batched CI tests without PC control.
+hipError_t launch_ci_batch(const uint8_t *data, int64_t ld, int64_t m, const uint8_t *cards,
+                           const CiTestDev *tests, const int32_t *zpool, int64_t n_tests,
+                           double alpha, Tile tile, CiOutDev *out, uint32_t *tables,
+                           const int64_t *table_off, int grid, hipStream_t s);
+
+// Plain per-test form: sample-parallel count of one test into per-block
+// partial tables, then a single-workgroup finish (fixed-order sum, FP64 G^2).
+struct PlainTest {
+    int32_t vars[kMaxCols];
+    int32_t ncols;
+    int32_t pad;
+};
+hipError_t launch_plain_count(const uint8_t *data, int64_t ld, int64_t m, const uint8_t *cards,
+                              const PlainTest &t, int64_t samples_per_block, int nblocks,
+                              uint32_t *partials, int64_t T, int lds_words, hipStream_t s);
+hipError_t launch_plain_finish(const uint8_t *cards, const PlainTest &t, int nblocks,
+                               const uint32_t *partials, int64_t T, uint32_t *table_ws,
+                               double alpha, CiOutDev *out, hipStream_t s);
+
+// Checks every value against its cardinality; first offending flat index
+// (v * m + s) is atomically minimised into *bad (initialised to INT64_MAX).
+hipError_t launch_validate(const uint8_t *data, int64_t ld, int64_t m, int32_t n,
+                           const uint8_t *cards, unsigned long long *bad, hipStream_t s);
+
+}  // namespace bns

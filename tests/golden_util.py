@@ -1,0 +1,53 @@
+"""Loading and comparing the stored oracle outputs in tests/golden/.
+
+The files are written by tests/golden/make_golden.py, which calls only the
+oracle and the synthetic-input generator.
+"""
+
+import gzip
+import json
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def load_golden(k: int):
+    with gzip.open(os.path.join(GOLDEN, f"cfg{k}.json.gz"), "rt") as f:
+        return json.load(f)
+
+
+def expand(entry):
+    """(adj, depth, sepsets) arrays/dict of one golden dataset entry."""
+    n = entry["n_vars"]
+    adj = np.zeros((n, n), dtype=np.uint8)
+    for i, j in entry["kept_edges"]:
+        adj[i, j] = adj[j, i] = 1
+    depth = np.full((n, n), -1, dtype=np.int32)
+    sep = {}
+    for i, j, d, S in entry["removals"]:
+        depth[i, j] = depth[j, i] = d
+        sep[(i, j)] = tuple(S)
+    for i in range(n):
+        for j in range(i + 1, n):
+            if not adj[i, j] and depth[i, j] < 0:
+                depth[i, j] = depth[j, i] = 0
+                sep[(i, j)] = ()
+    return adj, depth, sep
+
+
+def compare_skeleton(got, entry, label=""):
+    """Asserts identical skeleton, removal depths and sepsets, and that the
+    per-depth canonical test counts equal the oracle's."""
+    adj, depth, sep = expand(entry)
+    assert got.adj.shape == adj.shape, label
+    diff = np.argwhere(got.adj != adj)
+    assert diff.size == 0, f"{label}: skeleton differs at {diff[:5].tolist()}"
+    ddiff = np.argwhere(got.depth != depth)
+    assert ddiff.size == 0, f"{label}: removal depth differs at {ddiff[:5].tolist()}"
+    assert got.sepsets == sep, f"{label}: sepsets differ"
+    req = [s["tests_required"] for s in got.stats]
+    assert req == entry["tests_per_depth"], f"{label}: tests per depth {req} vs {entry['tests_per_depth']}"
+    rem = [s["removed"] for s in got.stats]
+    assert rem == entry["removed_per_depth"], f"{label}: removed per depth {rem} vs {entry['removed_per_depth']}"
