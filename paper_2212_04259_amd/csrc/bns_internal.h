@@ -8,12 +8,17 @@ namespace bns {
 
 constexpr int kWG = 256;            // threads per workgroup (4 wave64)
 constexpr int kWaves = kWG / 64;
-constexpr int kMaxZ = 30;           // largest conditioning set a kernel accepts
+// Largest conditioning set a kernel accepts.  Tables are limited to 2^24
+// cells and, from depth 1 on, every conditioning variable has at least two
+// categories (a one-category variable fails no test and leaves the graph at
+// depth 0), so no admissible test has more than 22 conditioning variables.
+constexpr int kMaxZ = 22;
 constexpr int kMaxCols = kMaxZ + 2;
 constexpr int kBinomK = kMaxZ + 1;  // binomial table columns: k = 0..kMaxZ
 constexpr int kMaxLevels = 64;      // ticket levels: level L holds test ranks [2^L - 1, 2^(L+1) - 1)
 constexpr uint32_t kMaxCells = 1u << 24;  // largest contingency table (cells)
 constexpr int kMaxDepths = 64;      // depth records kept per search
+constexpr int kSlotsPerWave = 8;    // tickets decoded per grab, per wave
 
 // Status codes written by kernels into the control block.
 enum DevError : int32_t { kDevOk = 0, kDevTableTooLarge = 1, kDevTooManyTests = 2, kDevDepthTooLarge = 3 };
@@ -38,6 +43,8 @@ struct EdgeRec {
     int32_t posj;         // position of j in the frozen list a(i)
     int32_t posi;         // position of i in a(j)
     int32_t levels;       // number of ticket levels the edge takes part in
+    int32_t pA;           // |a(i)\{j}|
+    int32_t pB;           // |a(j)\{i}|
     uint64_t nA;          // tests on side A (subsets of a(i)\{j})
     uint64_t n;           // all tests of the edge
 };
@@ -63,6 +70,11 @@ struct Ctl {
     unsigned long long total_tickets;
     unsigned long long ticket_ctr;
     unsigned long long pool_used;      // sepset members written so far
+    unsigned int apply_done;           // blocks of the removal kernel that finished
+    int32_t maxdeg;                    // largest frozen adjacency set at this depth
+    int32_t mode;                      // test kernel: 0 one test per wave, 1 per workgroup
+    int32_t batch;                     // tickets taken per grab
+    int32_t pad2;
     unsigned long long level_base[kMaxLevels + 1];
     unsigned long long level_cnt[kMaxLevels + 1];
     unsigned int hist[kMaxLevels + 2];

@@ -103,6 +103,18 @@ struct DevBuf {
     T *as() const { return static_cast<T *>(p); }
 };
 
+struct GraphEntry {
+    DepthArgs args;
+    int grid = 0;
+    int K = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~GraphEntry() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
 // Per-device state: properties, a library stream, and grow-only workspaces.
 struct DevCtx {
     int device = -1;
@@ -111,12 +123,24 @@ struct DevCtx {
     hipStream_t stream = nullptr;
     std::mutex mu;
     // skeleton search
-    DevBuf probs, var2prob, cards, binom, adj, nbr, deg, rowcnt, rowbase, edges_tmp, edges,
-        min_accept, rdepth, sepoff, pool, ctl;
+    DevBuf setup, adj, nbr, deg, rowcnt, rowbase, edges_tmp, edges, min_accept, rdepth, pool, ctl;
     // CI batch and plain form
     DevBuf ci_tests, ci_z, ci_out, ci_tab, ci_taboff, plain_part, plain_ws, plain_out;
     CiOutDev *h_out = nullptr;  // pinned readback slot
     Ctl *h_ctl = nullptr;       // pinned control-block readback
+    void *hpin = nullptr;       // pinned staging for uploads and result downloads
+    size_t hpin_bytes = 0;
+    hipError_t pinned(size_t n) {
+        if (n <= hpin_bytes && hpin) return hipSuccess;
+        if (hpin) (void)hipHostFree(hpin);
+        hpin = nullptr;
+        hpin_bytes = 0;
+        const size_t want = std::max<size_t>(n, 1 << 16);
+        hipError_t e = hipHostMalloc(&hpin, want, hipHostMallocDefault);
+        if (e == hipSuccess) hpin_bytes = want;
+        return e;
+    }
+    std::vector<std::unique_ptr<GraphEntry>> graphs;  // captured depth launches
 };
 
 static std::mutex g_ctx_mu;
@@ -272,7 +296,7 @@ extern "C" void bns_dataset_free(bns_dataset *ds) { delete ds; }
 // ---------------------------------------------------------------------------
 // Tiles
 // ---------------------------------------------------------------------------
-static const int kDefaultLdsBytes = 48 << 10;
+static const int kDefaultLdsBytes = 40 << 10;
 
 static bns_status make_tile(const DevCtx &dc, const bns_options &o, Tile *t) {
     int lds = o.lds_bytes ? o.lds_bytes : kDefaultLdsBytes;
@@ -300,7 +324,8 @@ static bns_status check_table(const std::vector<uint8_t> &cards, int x, int y, c
         T *= cards[z[k]];
         if (T > kMaxCells) return fail(BNS_E_TABLE_TOO_LARGE, "table of test %d-%d exceeds %u cells", x, y, kMaxCells);
     }
-    if (rxy + cards[x] + cards[y] + 1 > (uint64_t)tile.lds_words)
+    // one stratum (table + marginals) plus the spill words must fit a wave's slice
+    if (rxy + cards[x] + cards[y] + 1 + 64 > (uint64_t)(tile.lds_words / kWaves))
         return fail(BNS_E_TABLE_TOO_LARGE, "r_x * r_y of test %d-%d exceeds the LDS budget", x, y);
     return BNS_OK;
 }
@@ -379,7 +404,7 @@ extern "C" bns_status bns_ci_batch(const bns_dataset *ds, const bns_ci_test *tes
         d_taboff = dc->ci_taboff.as<int64_t>();
     }
     const int wg = std::max(1, depth_tests_max_wg_per_cu(tile.lds_words * 4));
-    const int grid = (int)std::min<int64_t>(n_tests, (int64_t)dc->num_cu * wg);
+    const int grid = (int)std::min<int64_t>((n_tests + kWaves - 1) / kWaves, (int64_t)dc->num_cu * wg);
     HIP_TRY(launch_ci_batch(ds->d_data, ds->ld, ds->m, ds->d_cards, dc->ci_tests.as<CiTestDev>(),
                             dc->ci_z.as<int32_t>(), n_tests, alpha, tile, dc->ci_out.as<CiOutDev>(),
                             d_tab, d_taboff, grid, s));
@@ -486,14 +511,38 @@ static bns_status dev_error(int32_t e) {
     }
 }
 
-struct Graph {
-    hipGraphExec_t exec = nullptr;
-    hipGraph_t graph = nullptr;
-    ~Graph() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
+static const int kDepthsPerLaunch = 4;
+
+// Captures (once per distinct argument set) K consecutive depth sequences as
+// one executable graph; the depth index lives in the device control block, so
+// the same graph serves every starting depth.
+static bns_status depth_graph(DevCtx &dc, const DepthArgs &a, int grid, int K, hipStream_t s,
+                              hipGraphExec_t *out) {
+    for (auto &g : dc.graphs)
+        if (g->K == K && g->grid == grid && std::memcmp(&g->args, &a, sizeof(a)) == 0) {
+            *out = g->exec;
+            return BNS_OK;
+        }
+    std::unique_ptr<GraphEntry> g(new GraphEntry());
+    g->args = a;
+    g->grid = grid;
+    g->K = K;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < K && e == hipSuccess; ++i) {
+        e = launch_depth_prepare(a, s);
+        if (e == hipSuccess) e = launch_depth_tests(a, grid, s);
+        if (e == hipSuccess) e = launch_depth_apply(a, s);
     }
-};
+    hipError_t e2 = hipStreamEndCapture(s, &g->graph);
+    HIP_TRY(e);
+    HIP_TRY(e2);
+    HIP_TRY(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    if (dc.graphs.size() >= 8) dc.graphs.erase(dc.graphs.begin());
+    *out = g->exec;
+    dc.graphs.push_back(std::move(g));
+    return BNS_OK;
+}
 
 static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t P,
                               const double *alpha, const int32_t *maxd, const bns_options &o,
@@ -525,14 +574,27 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     const int brows = nmax + 1;
     build_binom(brows, B);
 
-    HIP_TRY(dc.probs.ensure(sizeof(ProbDev) * (size_t)P));
-    HIP_TRY(dc.var2prob.ensure(sizeof(int32_t) * (size_t)G));
-    HIP_TRY(dc.cards.ensure((size_t)G));
-    HIP_TRY(dc.binom.ensure(sizeof(uint64_t) * B.size()));
+    // One packed upload: problems, variable -> problem map, cardinalities,
+    // binomial table (8-byte aligned sections).
+    auto al8 = [](size_t x) { return (x + 7) & ~(size_t)7; };
+    const size_t o_probs = 0;
+    const size_t o_binom = al8(o_probs + sizeof(ProbDev) * (size_t)P);
+    const size_t o_v2p = al8(o_binom + sizeof(uint64_t) * B.size());
+    const size_t o_cards = al8(o_v2p + sizeof(int32_t) * (size_t)G);
+    const size_t setup_bytes = al8(o_cards + (size_t)G);
+    HIP_TRY(dc.setup.ensure(setup_bytes));
+    HIP_TRY(dc.pinned(setup_bytes));
+    {
+        char *h = (char *)dc.hpin;
+        std::memcpy(h + o_probs, probs.data(), sizeof(ProbDev) * (size_t)P);
+        std::memcpy(h + o_binom, B.data(), sizeof(uint64_t) * B.size());
+        std::memcpy(h + o_v2p, var2prob.data(), sizeof(int32_t) * (size_t)G);
+        std::memcpy(h + o_cards, gcards.data(), (size_t)G);
+    }
+    HIP_TRY(hipMemcpyAsync(dc.setup.p, dc.hpin, setup_bytes, hipMemcpyHostToDevice, s));
     HIP_TRY(dc.adj.ensure((size_t)adj_total));
     HIP_TRY(dc.nbr.ensure(sizeof(int32_t) * (size_t)adj_total));
-    HIP_TRY(dc.rdepth.ensure(sizeof(int32_t) * (size_t)adj_total));
-    HIP_TRY(dc.sepoff.ensure(sizeof(int64_t) * (size_t)adj_total));
+    HIP_TRY(dc.rdepth.ensure((size_t)adj_total));
     HIP_TRY(dc.deg.ensure(sizeof(int32_t) * (size_t)G));
     HIP_TRY(dc.rowcnt.ensure(sizeof(int32_t) * (size_t)G));
     HIP_TRY(dc.rowbase.ensure(sizeof(int64_t) * (size_t)G));
@@ -541,18 +603,15 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     HIP_TRY(dc.min_accept.ensure(sizeof(unsigned long long) * (size_t)pairs_total));
     HIP_TRY(dc.ctl.ensure(sizeof(Ctl)));
     HIP_TRY(dc.pool.ensure(sizeof(int32_t) * 1024));
-    HIP_TRY(hipMemcpyAsync(dc.probs.p, probs.data(), sizeof(ProbDev) * (size_t)P, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(dc.var2prob.p, var2prob.data(), sizeof(int32_t) * (size_t)G, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(dc.cards.p, gcards.data(), (size_t)G, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(dc.binom.p, B.data(), sizeof(uint64_t) * B.size(), hipMemcpyHostToDevice, s));
 
     DepthArgs a;
-    a.probs = dc.probs.as<ProbDev>();
+    std::memset(&a, 0, sizeof(a));
+    a.probs = (const ProbDev *)(dc.setup.as<char>() + o_probs);
     a.n_probs = P;
     a.n_globals = G;
-    a.var2prob = dc.var2prob.as<int32_t>();
-    a.cards = dc.cards.as<uint8_t>();
-    a.binom = dc.binom.as<uint64_t>();
+    a.var2prob = (const int32_t *)(dc.setup.as<char>() + o_v2p);
+    a.cards = (const uint8_t *)(dc.setup.as<char>() + o_cards);
+    a.binom = (const uint64_t *)(dc.setup.as<char>() + o_binom);
     a.binom_rows = brows;
     a.pad = 0;
     a.adj = dc.adj.as<uint8_t>();
@@ -563,8 +622,7 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     a.edges_tmp = dc.edges_tmp.as<EdgeRec>();
     a.edges = dc.edges.as<EdgeRec>();
     a.min_accept = dc.min_accept.as<unsigned long long>();
-    a.rdepth = dc.rdepth.as<int32_t>();
-    a.sepoff = dc.sepoff.as<int64_t>();
+    a.rdepth = dc.rdepth.as<int8_t>();
     a.pool = dc.pool.as<int32_t>();
     a.ctl = dc.ctl.as<Ctl>();
     a.tile = tile;
@@ -572,6 +630,9 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     const int lds_bytes = tile.lds_words * 4;
     int wg = o.wg_per_cu ? o.wg_per_cu : depth_tests_max_wg_per_cu(lds_bytes);
     const int grid = std::max(1, dc.num_cu * wg);
+    a.test_waves = grid * kWaves;
+    a.n_pairs = pairs_total;
+    a.edge_grid = (int)std::max<int64_t>(1, std::min<int64_t>(512, (pairs_total + kWG - 1) / kWG));
 
     HIP_TRY(launch_init_search(a, s));
 
@@ -588,18 +649,27 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
         }
     } evg{ev0, ev1};
 
-    std::unique_ptr<Graph> graph;
-    int32_t* graph_pool = nullptr;
+    // Depths run in launches of up to kDepthsPerLaunch depth sequences; the
+    // host reads the control block once per launch.  A depth with no tests
+    // marks the search done and the kernels of any later sequence in the same
+    // launch return at once.
     const bool use_graph = o.use_graph && !o.timing;
-
+    const int per_launch = use_graph ? kDepthsPerLaunch : 1;
     std::vector<bns_depth_stats> stats;
-    unsigned long long alive = (unsigned long long)pairs_total;  // edges alive at the next depth
+    unsigned long long alive = (unsigned long long)pairs_total;  // edges alive at depth d
     unsigned long long pool_used = 0;
-    for (int d = 0;; ++d) {
+    int d = 0;
+    for (;;) {
         if (!unbounded && d > dmax) break;
         if (d >= kMaxDepths) return fail(BNS_E_TABLE_TOO_LARGE, "the search exceeds %d depths", kMaxDepths);
-        // Sepset slots for every edge that may be removed at this depth.
-        const size_t need = (size_t)(pool_used + alive * (unsigned long long)d);
+        int K = per_launch;
+        if (!unbounded) K = std::min(K, dmax + 1 - d);
+        K = std::min(K, kMaxDepths - d);
+        // Sepset slots for every edge that may be removed in these depths.
+        unsigned long long slots = 0;
+        for (int i = 0; i < K; ++i)
+            if (d + i > 0) slots += alive * (unsigned long long)(d + i + 3);
+        const size_t need = (size_t)(pool_used + slots);
         if (need > dc.pool.bytes / sizeof(int32_t)) {
             DevBuf nb;
             HIP_TRY(nb.ensure(sizeof(int32_t) * std::max(need, 2 * dc.pool.bytes / sizeof(int32_t))));
@@ -611,21 +681,10 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
             a.pool = dc.pool.as<int32_t>();
         }
         if (use_graph) {
-            if (!graph || graph_pool != a.pool) {
-                graph.reset(new Graph());
-                HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                hipError_t e1 = launch_depth_prepare(a, s);
-                hipError_t e2 = launch_depth_tests(a, grid, s);
-                hipError_t e3 = launch_depth_apply(a, s);
-                hipError_t e4 = hipStreamEndCapture(s, &graph->graph);
-                HIP_TRY(e1);
-                HIP_TRY(e2);
-                HIP_TRY(e3);
-                HIP_TRY(e4);
-                HIP_TRY(hipGraphInstantiate(&graph->exec, graph->graph, nullptr, nullptr, 0));
-                graph_pool = a.pool;
-            }
-            HIP_TRY(hipGraphLaunch(graph->exec, s));
+            hipGraphExec_t exec = nullptr;
+            st = depth_graph(dc, a, grid, K, s, &exec);
+            if (st != BNS_OK) return st;
+            HIP_TRY(hipGraphLaunch(exec, s));
         } else {
             HIP_TRY(launch_depth_prepare(a, s));
             if (o.timing) HIP_TRY(hipEventRecord(ev0, s));
@@ -637,59 +696,77 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
         HIP_TRY(hipStreamSynchronize(s));
         const Ctl &c = *dc.h_ctl;
         if (c.error) return dev_error(c.error);
-        if (c.done) break;
-        const DepthStatDev &sd = c.stats[d];
-        bns_depth_stats r;
-        std::memset(&r, 0, sizeof(r));
-        r.depth = d;
-        r.edges = (int64_t)sd.edges;
-        r.tests_required = (int64_t)sd.required;
-        r.tests_executed = (int64_t)sd.executed;
-        r.removed = (int64_t)sd.removed;
-        r.rechecks = (int64_t)sd.rechecks;
-        r.tickets = (int64_t)sd.tickets;
-        r.operand_bytes = sd.operand_bytes;
-        if (o.timing) {
-            float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
-            r.kernel_seconds = ms * 1e-3;
+        const int reached = c.depth;  // depths d .. reached-1 completed
+        for (int dd = d; dd < reached; ++dd) {
+            const DepthStatDev &sd = c.stats[dd];
+            bns_depth_stats r;
+            std::memset(&r, 0, sizeof(r));
+            r.depth = dd;
+            r.edges = (int64_t)sd.edges;
+            r.tests_required = (int64_t)sd.required;
+            r.tests_executed = (int64_t)sd.executed;
+            r.removed = (int64_t)sd.removed;
+            r.rechecks = (int64_t)sd.rechecks;
+            r.tickets = (int64_t)sd.tickets;
+            r.operand_bytes = sd.operand_bytes;
+            if (o.timing) {
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
+                r.kernel_seconds = ms * 1e-3;
+            }
+            stats.push_back(r);
+            alive = sd.edges - sd.removed;
         }
-        stats.push_back(r);
-        alive = sd.edges - sd.removed;
         pool_used = c.pool_used;
+        if (c.done) break;
+        if (reached != d + K) return fail(BNS_E_INTERNAL, "depth counter %d after launch from %d", reached, d);
+        d = reached;
     }
 
-    // Results: adjacency, removal depths, sepset offsets and members.
-    std::vector<uint8_t> hadj((size_t)adj_total);
-    std::vector<int32_t> hdep((size_t)adj_total);
-    std::vector<int64_t> hoff((size_t)adj_total);
-    std::vector<int32_t> hpool((size_t)std::max<unsigned long long>(pool_used, 1));
-    HIP_TRY(hipMemcpyAsync(hadj.data(), dc.adj.p, hadj.size(), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(hdep.data(), dc.rdepth.p, hdep.size() * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(hoff.data(), dc.sepoff.p, hoff.size() * 8, hipMemcpyDeviceToHost, s));
-    if (pool_used)
-        HIP_TRY(hipMemcpyAsync(hpool.data(), dc.pool.p, (size_t)pool_used * 4, hipMemcpyDeviceToHost, s));
+    // Results: removal depths (int8 per pair; -1 = kept) and the removal
+    // records of depth >= 1, in one pinned download.
+    const size_t rbytes = ((size_t)adj_total + 7) & ~(size_t)7;
+    const size_t pbytes = sizeof(int32_t) * (size_t)pool_used;
+    HIP_TRY(dc.pinned(rbytes + pbytes));
+    char *hres = (char *)dc.hpin;
+    HIP_TRY(hipMemcpyAsync(hres, dc.rdepth.p, (size_t)adj_total, hipMemcpyDeviceToHost, s));
+    if (pool_used) HIP_TRY(hipMemcpyAsync(hres + rbytes, dc.pool.p, pbytes, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    const int8_t *hdep = (const int8_t *)hres;
+    const int32_t *hpool = (const int32_t *)(hres + rbytes);
+    std::vector<std::unique_ptr<bns_skeleton>> sks((size_t)P);
     for (int32_t k = 0; k < P; ++k) {
-        std::unique_ptr<bns_skeleton> sk(new bns_skeleton());
+        sks[k].reset(new bns_skeleton());
+        bns_skeleton *sk = sks[k].get();
         const int n = ds[k]->n;
         const int64_t base = probs[k].adj_off, nn = (int64_t)n * n;
         sk->n = n;
-        sk->adj.assign(hadj.begin() + base, hadj.begin() + base + nn);
-        sk->depth.assign(hdep.begin() + base, hdep.begin() + base + nn);
+        sk->adj.assign((size_t)nn, 0);
+        sk->depth.assign((size_t)nn, -1);
         sk->sepoff.assign((size_t)nn, -1);
-        for (int i = 0; i < n; ++i)
-            for (int j = i + 1; j < n; ++j) {
-                const int64_t ij = (int64_t)i * n + j, ji = (int64_t)j * n + i;
-                const int32_t dd = sk->depth[ij];
-                if (dd < 0) continue;
-                const int64_t src = hoff[base + ij];
-                sk->sepoff[ij] = sk->sepoff[ji] = (int64_t)sk->pool.size();
-                for (int q = 0; q < dd; ++q) sk->pool.push_back(hpool[src + q]);
-            }
+        for (int64_t e = 0; e < nn; ++e) {
+            const int8_t dd = hdep[base + e];
+            sk->depth[e] = dd;
+            const int64_t i = e / n, j = e - i * n;
+            sk->adj[e] = (dd < 0 && i != j) ? 1 : 0;
+            if (dd == 0) sk->sepoff[e] = 0;  // empty set
+        }
         sk->stats = stats;
-        outs[k] = sk.release();
     }
+    for (unsigned long long q = 0; q < pool_used;) {
+        const int32_t k = hpool[q], i = hpool[q + 1], j = hpool[q + 2];
+        if (k < 0 || k >= P) return fail(BNS_E_INTERNAL, "corrupt removal record");
+        bns_skeleton *sk = sks[k].get();
+        const int n = sk->n;
+        const int32_t dd = sk->depth[(int64_t)i * n + j];
+        if (dd <= 0) return fail(BNS_E_INTERNAL, "removal record for a pair not removed at depth >= 1");
+        const int64_t off = (int64_t)sk->pool.size();
+        sk->pool.insert(sk->pool.end(), hpool + q + 3, hpool + q + 3 + dd);
+        sk->sepoff[(int64_t)i * n + j] = off;
+        sk->sepoff[(int64_t)j * n + i] = off;
+        q += (unsigned long long)dd + 3;
+    }
+    for (int32_t k = 0; k < P; ++k) outs[k] = sks[k].release();
     return BNS_OK;
 }
 

@@ -6,6 +6,9 @@
 // samples with X = x, Y = y, Z = z; E_xyz = N_x+z N_+yz / N_++z;
 // G^2 = 2 sum N ln(N / E); p from the chi-square distribution with
 // (r_X - 1)(r_Y - 1) prod r_Z degrees of freedom; independence iff p > alpha.
+//
+// A test is run by a group of lanes (Grp): one wave64, or a whole workgroup
+// when one test must be finished by many lanes.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,22 +17,23 @@
 
 #include "bns_internal.h"
 
+#define BNS_INLINE __device__ __forceinline__
+
 namespace bns {
 
 // ---------------------------------------------------------------------------
-// Per-test description staged in LDS (filled by the kernel before a test).
+// Per-test description staged in LDS (one per group).
 // ---------------------------------------------------------------------------
 struct TestSh {
     const uint8_t *col[kMaxCols];  // x, y, z_1..z_d columns
     uint32_t card[kMaxCols];
     uint32_t mult[kMaxCols];       // cell stride of each column: 1, r_x, r_x r_y, ...
     int32_t ncols;                 // d + 2
-    int32_t pad;
     int64_t m;                     // samples
     double red_d[kWaves];
     float red_f[kWaves];
     double bcast_d[2];
-    int32_t bcast_i[4];
+    int32_t bcast_i[2];
 };
 
 struct TestOut {
@@ -41,39 +45,61 @@ struct TestOut {
 };
 
 // ---------------------------------------------------------------------------
-// Workgroup reductions in a fixed order (deterministic results).
+// Groups.  Reductions use a fixed order and broadcast lane 0's result, so
+// every lane sees the same, run-to-run deterministic value.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ inline T wave_sum(T v) {
+BNS_INLINE T wave_sum(T v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    return __shfl(v, 0, 64);
 }
 
-__device__ inline double wg_sum(double v, TestSh &t) {
-    v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0) t.red_d[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double s = 0.0;
+// A group of lanes running one test: a wave (block == false; several
+// independent tests per workgroup, no workgroup barriers) or the whole
+// workgroup (block == true).  The choice is uniform over the group, so the
+// branches below never diverge.
+struct Grp {
+    int rank;
+    int size;
+    bool block;
+    BNS_INLINE static Grp wave() { return Grp{(int)(threadIdx.x & 63), 64, false}; }
+    BNS_INLINE static Grp workgroup() { return Grp{(int)threadIdx.x, kWG, true}; }
+    BNS_INLINE void sync() const {
+        if (block) {
+            __syncthreads();
+        } else {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    BNS_INLINE double sum(double v, TestSh &t) const {
+        v = wave_sum(v);
+        if (!block) return v;
+        if ((threadIdx.x & 63) == 0) t.red_d[threadIdx.x >> 6] = v;
+        __syncthreads();
+        double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) s += t.red_d[w];
-    __syncthreads();
-    return s;
-}
-
-__device__ inline float wg_sum(float v, TestSh &t) {
-    v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0) t.red_f[threadIdx.x >> 6] = v;
-    __syncthreads();
-    float s = 0.0f;
+        for (int w = 0; w < kWaves; ++w) s += t.red_d[w];
+        __syncthreads();
+        return s;
+    }
+    BNS_INLINE float sum(float v, TestSh &t) const {
+        v = wave_sum(v);
+        if (!block) return v;
+        if ((threadIdx.x & 63) == 0) t.red_f[threadIdx.x >> 6] = v;
+        __syncthreads();
+        float s = 0.0f;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) s += t.red_f[w];
-    __syncthreads();
-    return s;
-}
+        for (int w = 0; w < kWaves; ++w) s += t.red_f[w];
+        __syncthreads();
+        return s;
+    }
+};
 
 // Exact quotient i / d for i < 2^24 via a float reciprocal and one correction.
-__device__ inline uint32_t fast_div(uint32_t i, uint32_t d, float inv) {
+BNS_INLINE uint32_t fast_div(uint32_t i, uint32_t d, float inv) {
     uint32_t q = (uint32_t)((float)i * inv);
     if (q * d > i) {
         --q;
@@ -84,35 +110,56 @@ __device__ inline uint32_t fast_div(uint32_t i, uint32_t d, float inv) {
 }
 
 // ---------------------------------------------------------------------------
-// Chi-square upper tail in FP64: p = Q(a, x) with a = df/2, x = G^2/2.
-// Lower regularised gamma from its power series when x < a + 1, else the
-// upper one from the Legendre continued fraction (modified Lentz).
+// Chi-square upper tail in FP64: p = Q(a, x) with a = df/2, x = G^2/2, and
+// the Gamma(a, 1) density at x (the slope of Q, used to propagate G^2 error
+// bounds), evaluated by all 64 lanes of a wave together; every lane returns
+// the same values.
+//
+// df <= 128 uses the closed forms for integer and half-integer a:
+//   a = n:       Q = e^-x sum_{k<n} x^k / k!
+//   a = n + 1/2: Q = erfc(sqrt x) + e^-x sum_{k<n} x^(k+1/2) / Gamma(k + 3/2)
+// whose terms are formed as a prefix product across lanes (term_k =
+// term_{k-1} * x / (k or k + 1/2)).  All summands are positive.
+// Larger df: for x below a + 1 + 3 sqrt(a) the lower regularised gamma is
+// summed from its power series P = x^a e^-x / Gamma(a+1) sum_k x^k /
+// ((a+1)...(a+k)), lane l taking terms [lK, lK + K) from a start formed with
+// lgamma; p = 1 - P.  Above it, Legendre's continued fraction for Gamma(a, x)
+// (modified Lentz) gives Q directly.
 // ---------------------------------------------------------------------------
-static __device__ __noinline__ double chi2_upper(int64_t df, double g2) {
-    if (df <= 0) return 1.0;
+struct Tail {
+    double p;
+    double dens;
+};
+
+// Large df (> 128): series or continued fraction, out of line (rare).
+static __device__ __noinline__ Tail chi2_tail_large(int64_t df, double x) {
+    Tail r;
+    const int lane = threadIdx.x & 63;
     const double a = 0.5 * (double)df;
-    const double x = 0.5 * g2;
-    if (!(x > 0.0)) return 1.0;
-    const double log_front = a * log(x) - x - lgamma(a);  // log(x^a e^-x / Gamma(a))
-    if (x < a + 1.0) {
-        // gamma(a,x)/Gamma(a) = x^a e^-x / Gamma(a) * sum_k x^k / (a (a+1) ... (a+k))
-        double term = 1.0 / a, acc = term, den = a;
-        for (int k = 0; k < 200000; ++k) {
-            den += 1.0;
-            term *= x / den;
-            acc += term;
-            if (term <= acc * 1.1102230246251565e-16) break;
+    const double lx = log(x);
+    r.dens = exp((a - 1.0) * lx - x - lgamma(a));
+    if (x < a + 1.0 + 3.0 * sqrt(a)) {
+        const double need = fmax(x - a, 0.0) + 10.0 * sqrt(a + x + 1.0) + 40.0;
+        const int K = (int)ceil(need / 64.0);
+        const double lg1 = lgamma(a + 1.0);
+        const double k0 = (double)lane * (double)K;
+        double term = exp(k0 * lx - (lgamma(a + 1.0 + k0) - lg1));
+        double s = 0.0;
+        for (int j = 0; j < K; ++j) {
+            s += term;
+            term *= x / (a + 1.0 + k0 + (double)j);
         }
-        double lower = exp(log_front) * acc;
-        return lower >= 1.0 ? 0.0 : 1.0 - lower;
+        const double tot = wave_sum(s);
+        const double lower = exp(a * lx - x - lg1) * tot;
+        r.p = lower >= 1.0 ? 0.0 : 1.0 - lower;
+        return r;
     }
-    // Gamma(a,x)/Gamma(a) = x^a e^-x / Gamma(a) / (x+1-a - 1(1-a)/(x+3-a - 2(2-a)/(x+5-a - ...)))
     const double fpmin = 1e-300;
     double bk = x + 1.0 - a;
     double C = 1.0 / fpmin;
     double D = 1.0 / bk;
     double H = D;
-    for (int k = 1; k < 200000; ++k) {
+    for (int k = 1; k < 100000; ++k) {
         const double ak = (double)k * (a - (double)k);
         bk += 2.0;
         D = bk + ak * D;
@@ -124,13 +171,46 @@ static __device__ __noinline__ double chi2_upper(int64_t df, double g2) {
         H *= step;
         if (fabs(step - 1.0) <= 2.220446049250313e-16) break;
     }
-    return exp(log_front) * H;
+    r.p = exp(a * lx - x - lgamma(a)) * H;
+    return r;
 }
 
-// Density of Gamma(a, 1) at x (the derivative of Q(a, x) in x, up to sign).
-static __device__ __noinline__ double gamma_density(double a, double x) {
-    if (!(x > 0.0)) return 0.0;
-    return exp((a - 1.0) * log(x) - x - lgamma(a));
+static __device__ __noinline__ Tail chi2_tail_wave(int64_t df, double g2) {
+    Tail r;
+    r.p = 1.0;
+    r.dens = 0.0;
+    if (df <= 0) return r;
+    const double x = 0.5 * g2;
+    if (!(x > 0.0)) return r;
+    if (df > 128) return chi2_tail_large(df, x);
+    if (x > 700.0) {  // e^-x underflows; the tail is below 1e-200
+        r.p = 0.0;
+        return r;
+    }
+    const int lane = threadIdx.x & 63;
+    const double pi = 3.141592653589793;
+    const int n = (int)(df >> 1);
+    const bool odd = (df & 1) != 0;
+    double f;
+    if (lane == 0) f = odd ? 2.0 * sqrt(x / pi) : 1.0;
+    else f = x / ((double)lane + (odd ? 0.5 : 0.0));
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double o = __shfl_up(f, off, 64);
+        if (lane >= off) f *= o;
+    }
+    const double S = wave_sum((lane < n) ? f : 0.0);
+    const double last = __shfl(f, n > 0 ? n - 1 : 0, 64);
+    const double ex = exp(-x);
+    if (odd) {
+        r.p = erfc(sqrt(x)) + ex * S;
+        r.dens = (n > 0) ? ex * last : ex / sqrt(pi * x);
+    } else {
+        r.p = ex * S;
+        r.dens = ex * last;
+    }
+    if (r.p > 1.0) r.p = 1.0;
+    return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -158,7 +238,7 @@ struct TermCfg<double> {
 };
 
 template <typename Real>
-__device__ inline Real g2_half_term(uint32_t N, uint32_t nxz, uint32_t nyz, uint32_t nzz) {
+BNS_INLINE Real g2_half_term(uint32_t N, uint32_t nxz, uint32_t nyz, uint32_t nzz) {
     if (N == 0) return (Real)nxz * (Real)nyz / (Real)nzz;
     const uint64_t a = (uint64_t)N * nzz;
     const uint64_t b = (uint64_t)nxz * nyz;
@@ -179,118 +259,184 @@ __device__ inline Real g2_half_term(uint32_t N, uint32_t nxz, uint32_t nyz, uint
 // Counting (step (i) of Section IV-A) into an LDS table.
 //
 // Columns are uint8, read 16 samples per lane per column with coalesced
-// 16-byte loads.  Cell of a sample: sum_k value_k * mult_k.  Only cells in
-// [cbase, cbase + Tc) are counted (z-range chunking of large tables).  The
-// table is replicated 2^logR times, interleaved per cell (replica = lane bits)
-// so that lanes hitting the same cell usually hit different LDS words.
+// 16-byte loads.  Cell of a sample: sum_k value_k * mult_k.  The table is
+// replicated 2^logR times, interleaved per cell (replica = low lane bits), so
+// lanes hitting the same cell usually hit different LDS words and banks.
+// kChunk: only cells in [cbase, cbase + Tc) are counted (z-range passes of
+// tables larger than the LDS slice); other samples go to per-lane spill
+// words at `trash`, which keeps the increments unconditional.
 // ---------------------------------------------------------------------------
-__device__ inline uint32_t byte_of(const uint4 &v, int b) {
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+BNS_INLINE uint32_t byte_of(const u32x4 &v, int b) {
     const uint32_t w = (b < 4) ? v.x : (b < 8) ? v.y : (b < 12) ? v.z : v.w;
     return (w >> (8 * (b & 3))) & 0xffu;
 }
 
-template <int NC>
-__device__ inline void count_fixed(const TestSh &t, uint32_t *tab, uint32_t cbase, uint32_t Tc,
-                                   int logR, int64_t q0, int64_t q1) {
-    const uint32_t rep = threadIdx.x & ((1u << logR) - 1u);
-    const uint4 *cp[NC];
-    uint32_t mul[NC];
+// Global-memory view of a column pointer that is uniform across the wave:
+// kept in scalar registers, addressed with a 32-bit per-lane offset.
+typedef __attribute__((address_space(1))) const u32x4 gvec4;
+typedef __attribute__((address_space(1))) const uint32_t gword;
+
+BNS_INLINE const gvec4 *uniform_col(const uint8_t *p) {
+    const uint64_t a = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return (const gvec4 *)(((uint64_t)hi << 32) | lo);
+}
+
+template <int NC, bool kChunk>
+BNS_INLINE void count16(const u32x4 (&v)[NC], const uint32_t (&mul)[NC], uint32_t *tab,
+                        uint32_t cbase, uint32_t Tc, uint32_t trash, int logR, uint32_t rep,
+                        uint32_t spill) {
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-        cp[k] = reinterpret_cast<const uint4 *>(t.col[k]);
-        mul[k] = t.mult[k];
-    }
-    for (int64_t q = q0 + threadIdx.x; q < q1; q += kWG) {
-        uint4 v[NC];
+    for (int b = 0; b < 16; ++b) {
+        uint32_t cell = byte_of(v[0], b);
 #pragma unroll
-        for (int k = 0; k < NC; ++k) v[k] = cp[k][q];
-#pragma unroll
-        for (int b = 0; b < 16; ++b) {
-            uint32_t cell = byte_of(v[0], b);
-#pragma unroll
-            for (int k = 1; k < NC; ++k) cell += __umul24(byte_of(v[k], b), mul[k]);
+        for (int k = 1; k < NC; ++k) cell += __umul24(byte_of(v[k], b), mul[k]);
+        uint32_t addr;
+        if (kChunk) {
             const uint32_t idx = cell - cbase;
-            if (idx < Tc) atomicAdd(&tab[(idx << logR) | rep], 1u);
+            addr = (idx < Tc) ? ((idx << logR) | rep) : (trash + spill);
+        } else {
+            addr = (cell << logR) | rep;
         }
+        atomicAdd(&tab[addr], 1u);
     }
 }
 
-__device__ inline void count_generic(const TestSh &t, uint32_t *tab, uint32_t cbase, uint32_t Tc,
-                                     int logR, int64_t q0, int64_t q1) {
-    const uint32_t rep = threadIdx.x & ((1u << logR) - 1u);
+template <int NC, bool kChunk>
+BNS_INLINE void count_fixed(const TestSh &t, uint32_t *tab, uint32_t cbase, uint32_t Tc,
+                            uint32_t trash, int logR, int64_t q0, int64_t q1, int rank, int S) {
+    // groups of 16 samples per lane kept in flight per iteration
+    constexpr int U = (NC <= 3) ? 4 : 2;
+    const uint32_t rep = (uint32_t)rank & ((1u << logR) - 1u);
+    const uint32_t spill = (uint32_t)rank;
+    const gvec4 *cp[NC];
+    uint32_t mul[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        cp[k] = uniform_col(t.col[k]);
+        mul[k] = __builtin_amdgcn_readfirstlane(t.mult[k]);
+    }
+    // sample groups are < 2^27, so 32-bit group indices suffice
+    uint32_t q = (uint32_t)q0 + (uint32_t)rank;
+    const uint32_t qe = (uint32_t)q1;
+    const uint32_t us = (uint32_t)S;
+    for (; q + (U - 1) * us < qe; q += U * us) {
+        u32x4 v[U][NC];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < NC; ++k) v[u][k] = cp[k][q + u * us];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            count16<NC, kChunk>(v[u], mul, tab, cbase, Tc, trash, logR, rep, spill);
+    }
+    for (; q < qe; q += us) {
+        u32x4 v[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) v[k] = cp[k][q];
+        count16<NC, kChunk>(v, mul, tab, cbase, Tc, trash, logR, rep, spill);
+    }
+}
+
+template <bool kChunk>
+BNS_INLINE void count_generic(const TestSh &t, uint32_t *tab, uint32_t cbase, uint32_t Tc,
+                              uint32_t trash, int logR, int64_t q0, int64_t q1, int rank, int S) {
+    const uint32_t rep = (uint32_t)rank & ((1u << logR) - 1u);
+    const uint32_t spill = (uint32_t)rank;
     const int nc = t.ncols;
-    for (int64_t q = q0 + threadIdx.x; q < q1; q += kWG) {
+    for (int64_t q = q0 + rank; q < q1; q += S) {
+        uint32_t cell[16];
+        {
+            const u32x4 v = uniform_col(t.col[0])[q];
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            uint32_t cell[4];
-            {
-                const uint32_t v = reinterpret_cast<const uint32_t *>(t.col[0])[4 * q + w];
+            for (int b = 0; b < 16; ++b) cell[b] = byte_of(v, b);
+        }
+        for (int k = 1; k < nc; ++k) {
+            const u32x4 v = uniform_col(t.col[k])[q];
+            const uint32_t mk = __builtin_amdgcn_readfirstlane(t.mult[k]);
 #pragma unroll
-                for (int b = 0; b < 4; ++b) cell[b] = (v >> (8 * b)) & 0xffu;
-            }
-            for (int k = 1; k < nc; ++k) {
-                const uint32_t v = reinterpret_cast<const uint32_t *>(t.col[k])[4 * q + w];
-                const uint32_t mk = t.mult[k];
+            for (int b = 0; b < 16; ++b) cell[b] += __umul24(byte_of(v, b), mk);
+        }
 #pragma unroll
-                for (int b = 0; b < 4; ++b) cell[b] += __umul24((v >> (8 * b)) & 0xffu, mk);
-            }
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < 16; ++b) {
+            uint32_t addr;
+            if (kChunk) {
                 const uint32_t idx = cell[b] - cbase;
-                if (idx < Tc) atomicAdd(&tab[(idx << logR) | rep], 1u);
+                addr = (idx < Tc) ? ((idx << logR) | rep) : (trash + spill);
+            } else {
+                addr = (cell[b] << logR) | rep;
             }
+            atomicAdd(&tab[addr], 1u);
         }
     }
 }
 
 // Samples [s0, s1) one byte at a time (the ragged tail after the 16-sample groups).
-__device__ inline void count_tail(const TestSh &t, uint32_t *tab, uint32_t cbase, uint32_t Tc,
-                                  int logR, int64_t s0, int64_t s1) {
-    const uint32_t rep = threadIdx.x & ((1u << logR) - 1u);
-    for (int64_t s = s0 + threadIdx.x; s < s1; s += kWG) {
+template <bool kChunk>
+BNS_INLINE void count_tail(const TestSh &t, uint32_t *tab, uint32_t cbase, uint32_t Tc,
+                           uint32_t trash, int logR, int64_t s0, int64_t s1, int rank, int S) {
+    const uint32_t rep = (uint32_t)rank & ((1u << logR) - 1u);
+    for (int64_t s = s0 + rank; s < s1; s += S) {
         uint32_t cell = t.col[0][s];
         for (int k = 1; k < t.ncols; ++k) cell += __umul24((uint32_t)t.col[k][s], t.mult[k]);
-        const uint32_t idx = cell - cbase;
-        if (idx < Tc) atomicAdd(&tab[(idx << logR) | rep], 1u);
+        uint32_t addr;
+        if (kChunk) {
+            const uint32_t idx = cell - cbase;
+            addr = (idx < Tc) ? ((idx << logR) | rep) : (trash + (uint32_t)rank);
+        } else {
+            addr = (cell << logR) | rep;
+        }
+        atomicAdd(&tab[addr], 1u);
     }
 }
 
-// Counts samples [s0, s1) (s0 a multiple of 16).
-__device__ inline void count_samples(const TestSh &t, uint32_t *tab, uint32_t cbase, uint32_t Tc,
-                                     int logR, int64_t s0, int64_t s1) {
+// Counts samples [s0, s1) (s0 a multiple of 16) with the S lanes of a group.
+template <bool kChunk>
+BNS_INLINE void count_range(const TestSh &t, uint32_t *tab, uint32_t cbase, uint32_t Tc,
+                            uint32_t trash, int logR, int64_t s0, int64_t s1, int rank, int S) {
     const int64_t q0 = s0 >> 4, q1 = s1 >> 4;
     switch (t.ncols) {
-        case 2: count_fixed<2>(t, tab, cbase, Tc, logR, q0, q1); break;
-        case 3: count_fixed<3>(t, tab, cbase, Tc, logR, q0, q1); break;
-        case 4: count_fixed<4>(t, tab, cbase, Tc, logR, q0, q1); break;
-        case 5: count_fixed<5>(t, tab, cbase, Tc, logR, q0, q1); break;
-        case 6: count_fixed<6>(t, tab, cbase, Tc, logR, q0, q1); break;
-        default: count_generic(t, tab, cbase, Tc, logR, q0, q1); break;
+        case 2: count_fixed<2, kChunk>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
+        case 3: count_fixed<3, kChunk>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
+        case 4: count_fixed<4, kChunk>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
+        case 5: count_fixed<5, kChunk>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
+        case 6: count_fixed<6, kChunk>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
+        default: count_generic<kChunk>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
     }
-    if ((q1 << 4) < s1) count_tail(t, tab, cbase, Tc, logR, q1 << 4, s1);
+    if ((q1 << 4) < s1) count_tail<kChunk>(t, tab, cbase, Tc, trash, logR, q1 << 4, s1, rank, S);
 }
 
 // Sums the 2^logR interleaved replicas of each cell: out[c] = sum_r rep[c * R + r].
-__device__ inline void reduce_replicas(const uint32_t *rep_tab, uint32_t *out, uint32_t Tc,
-                                       int logR) {
-    const uint32_t R = 1u << logR;
-    const uint32_t total = Tc << logR;
-    const uint32_t lane = threadIdx.x & 63u;
-    for (uint32_t base = (threadIdx.x & ~63u); base < total; base += kWG) {
-        const uint32_t e = base + lane;
-        uint32_t v = (e < total) ? rep_tab[e] : 0u;
-        for (uint32_t off = 1; off < R; off <<= 1) v += __shfl_xor(v, (int)off, 64);
-        if ((lane & (R - 1u)) == 0u && e < total) out[e >> logR] = v;
+// Lane c starts at replica c mod R, so the lanes of a wave read R (up to 64)
+// different banks at every step.
+BNS_INLINE void reduce_replicas(const uint32_t *rep_tab, uint32_t *out, uint32_t Tc, int logR,
+                                int rank, int S) {
+    const uint32_t R = 1u << logR, mask = R - 1u;
+    for (uint32_t c = (uint32_t)rank; c < Tc; c += (uint32_t)S) {
+        const uint32_t *p = rep_tab + (c << logR);
+        uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        uint32_t r = 0;
+        for (; r + 4 <= R; r += 4) {
+            s0 += p[(r + c) & mask];
+            s1 += p[(r + 1 + c) & mask];
+            s2 += p[(r + 2 + c) & mask];
+            s3 += p[(r + 3 + c) & mask];
+        }
+        for (; r < R; ++r) s0 += p[(r + c) & mask];
+        out[c] = (s0 + s1) + (s2 + s3);
     }
 }
 
 // Marginal tables of a chunk of Zc strata (step (ii) of Section IV-A):
 // rows[x + rx z] = N_x+z, cols[y + ry z] = N_+yz, strata[z] = N_++z.
-__device__ inline void marginals(const uint32_t *tab, uint32_t *rows, uint32_t *cols,
-                                 uint32_t *strata, uint32_t rx, uint32_t ry, uint32_t Zc) {
+BNS_INLINE void marginals(const Grp &g, const uint32_t *tab, uint32_t *rows, uint32_t *cols,
+                          uint32_t *strata, uint32_t rx, uint32_t ry, uint32_t Zc) {
     const float inv_rx = 1.0f / (float)rx;
     const uint32_t nrow = rx * Zc, ncol = ry * Zc;
-    for (uint32_t i = threadIdx.x; i < nrow + ncol; i += kWG) {
+    for (uint32_t i = g.rank; i < nrow + ncol; i += g.size) {
         if (i < nrow) {
             const uint32_t z = fast_div(i, rx, inv_rx), xv = i - z * rx;
             const uint32_t *p = tab + xv + rx * ry * z;
@@ -305,22 +451,23 @@ __device__ inline void marginals(const uint32_t *tab, uint32_t *rows, uint32_t *
             cols[rho] = s;
         }
     }
-    __syncthreads();
-    for (uint32_t z = threadIdx.x; z < Zc; z += kWG) {
+    g.sync();
+    for (uint32_t z = g.rank; z < Zc; z += g.size) {
         uint32_t s = 0;
         for (uint32_t yv = 0; yv < ry; ++yv) s += cols[yv + ry * z];
         strata[z] = s;
     }
-    __syncthreads();
+    g.sync();
 }
 
-// This thread's part of sum of g2_half_term over the chunk.
+// This lane's part of the sum of g2_half_term over a chunk.
 template <typename Real>
-__device__ inline Real g2_partial(const uint32_t *tab, const uint32_t *rows, const uint32_t *cols,
-                                  const uint32_t *strata, uint32_t rx, uint32_t ry, uint32_t Zc) {
+BNS_INLINE Real g2_partial(const Grp &g, const uint32_t *tab, const uint32_t *rows,
+                           const uint32_t *cols, const uint32_t *strata, uint32_t rx, uint32_t ry,
+                           uint32_t Zc) {
     const float inv_ry = 1.0f / (float)ry;
     Real acc = 0;
-    for (uint32_t rho = threadIdx.x; rho < ry * Zc; rho += kWG) {
+    for (uint32_t rho = g.rank; rho < ry * Zc; rho += g.size) {
         const uint32_t z = fast_div(rho, ry, inv_ry);
         const uint32_t nzz = strata[z];
         if (nzz == 0) continue;
@@ -333,20 +480,21 @@ __device__ inline Real g2_partial(const uint32_t *tab, const uint32_t *rows, con
 }
 
 // ---------------------------------------------------------------------------
-// Chunk plan of a test: how many strata fit per LDS pass and the replication.
+// Pass plan of a test: strata per LDS pass and the replication of the table.
 // ---------------------------------------------------------------------------
 struct Plan {
     uint32_t rx, ry, rxy;
     uint32_t nstrata;     // prod r_z
     uint32_t T;           // cells
-    uint32_t zc_per;      // strata per chunk
+    uint32_t zc_per;      // strata per pass
     uint32_t nchunks;
-    int logR;             // replication of single-chunk tables
+    int logR;             // replication of single-pass tables
     int64_t df;
     int32_t err;
 };
 
-__device__ inline Plan make_plan(const TestSh &t, const Tile &tile) {
+// W: LDS words available to the group; S: lanes in the group.
+BNS_INLINE Plan make_plan(const TestSh &t, uint32_t W, int max_rep_log2, int S) {
     Plan P;
     P.err = kDevOk;
     P.rx = t.card[0];
@@ -364,98 +512,127 @@ __device__ inline Plan make_plan(const TestSh &t, const Tile &tile) {
     P.nstrata = (uint32_t)ns;
     P.T = P.rxy * P.nstrata;
     P.df = (int64_t)(P.rx - 1) * (int64_t)(P.ry - 1) * (int64_t)P.nstrata;
-    const uint32_t W = (uint32_t)tile.lds_words;
     const uint32_t per_stratum = P.rxy + P.rx + P.ry + 1;  // table + marginals
-    uint32_t zc = W / per_stratum;
-    if (zc == 0) {
-        P.err = kDevTableTooLarge;
-        zc = 1;
-    }
-    if (zc > P.nstrata) zc = P.nstrata;
-    P.zc_per = zc;
-    P.nchunks = (P.nstrata + zc - 1) / zc;
+    const uint32_t marg = (P.rx + P.ry + 1) * P.nstrata;
     P.logR = 0;
-    if (P.nchunks == 1) {
-        // Replicate while the replicated table still fits next to the reduced one
-        // and the zero/reduce work stays small against the m increments.
-        const uint32_t marg = (P.rx + P.ry + 1) * P.nstrata;
+    if ((uint64_t)P.T + marg <= W) {
+        P.zc_per = P.nstrata;
+        P.nchunks = 1;
+        // Replicate while the replicated table fits next to the reduced one
+        // and the zero/reduce work stays small against the increments.
         const int64_t m = t.m;
-        while (P.logR < tile.max_rep_log2) {
+        while (P.logR < max_rep_log2) {
             const uint64_t R2 = 2ull << P.logR;
             if ((uint64_t)P.T * R2 + P.T + marg > W) break;
-            if ((int64_t)(P.T * R2) * 4 > m) break;
+            if ((int64_t)(P.T * R2) * 4 > m + 16 * S) break;
             ++P.logR;
         }
+    } else {
+        // Passes over z ranges; S spill words follow the counted cells.
+        uint32_t zc = (W > (uint32_t)S) ? (W - (uint32_t)S) / per_stratum : 0;
+        if (zc == 0) {
+            P.err = kDevTableTooLarge;
+            zc = 1;
+        }
+        if (zc > P.nstrata) zc = P.nstrata;
+        P.zc_per = zc;
+        P.nchunks = (P.nstrata + zc - 1) / zc;
     }
     return P;
 }
 
-// Counts, marginals and the G^2 sum of one test over all its chunks in
-// precision Real.  Leaves the last chunk's table and marginals in LDS at
-// *tab_out / rows / cols / strata.  When gtab is not null the exact counts
-// are also written there (cell layout of the table).
-template <typename Real>
-__device__ inline double table_pass(TestSh &t, const Plan &P, uint32_t *lds, uint32_t *gtab,
-                                    const uint32_t **tab_out) {
-    Real part = 0;
+// Counts, marginals and the G^2 sum of one test over all its passes (G^2 in
+// FP64 when fp64, else FP32).  Leaves the last pass's table and marginals in
+// LDS (returned through *tab_out).  gtab (may be null) receives the counts.
+BNS_INLINE double table_pass(const Grp &g, TestSh &t, const Plan &P, uint32_t *lds, uint32_t *gtab,
+                             bool fp64, const uint32_t **tab_out) {
+    double part64 = 0.0;
+    float part32 = 0.0f;
     const uint32_t *tab = lds;
+    const bool chunked = P.nchunks > 1;
     for (uint32_t c = 0; c < P.nchunks; ++c) {
         const uint32_t z0 = c * P.zc_per;
         const uint32_t Zc = min(P.zc_per, P.nstrata - z0);
         const uint32_t Tc = P.rxy * Zc;
         const int logR = P.logR;
         uint32_t *rep_tab = lds;
-        uint32_t *red = (logR > 0) ? lds + (Tc << logR) : lds;
-        uint32_t *rows = red + Tc;
+        // layout: [replicated table | spill words (passes)] [reduced table (R > 1)]
+        //         [rows] [cols] [strata]
+        const uint32_t head = (Tc << logR) + (chunked ? (uint32_t)g.size : 0u);
+        uint32_t *red = (logR > 0) ? lds + head : lds;
+        uint32_t *rows = lds + head + (logR > 0 ? Tc : 0u);
         uint32_t *cols = rows + P.rx * Zc;
         uint32_t *strata = cols + P.ry * Zc;
-        for (uint32_t i = threadIdx.x; i < (Tc << logR); i += kWG) rep_tab[i] = 0u;
-        __syncthreads();
-        count_samples(t, rep_tab, P.rxy * z0, Tc, logR, 0, t.m);
-        __syncthreads();
+        for (uint32_t i = g.rank; i < head; i += g.size) rep_tab[i] = 0u;
+        g.sync();
+        if (chunked)
+            count_range<true>(t, rep_tab, P.rxy * z0, Tc, Tc, 0, 0, t.m, g.rank, g.size);
+        else
+            count_range<false>(t, rep_tab, 0, Tc, 0, logR, 0, t.m, g.rank, g.size);
+        g.sync();
         if (logR > 0) {
-            reduce_replicas(rep_tab, red, Tc, logR);
-            __syncthreads();
+            reduce_replicas(rep_tab, red, Tc, logR, g.rank, g.size);
+            g.sync();
         }
         if (gtab)
-            for (uint32_t i = threadIdx.x; i < Tc; i += kWG) gtab[P.rxy * z0 + i] = red[i];
-        marginals(red, rows, cols, strata, P.rx, P.ry, Zc);
-        part += g2_partial<Real>(red, rows, cols, strata, P.rx, P.ry, Zc);
+            for (uint32_t i = g.rank; i < Tc; i += g.size) gtab[P.rxy * z0 + i] = red[i];
+        marginals(g, red, rows, cols, strata, P.rx, P.ry, Zc);
+        if (fp64) part64 += g2_partial<double>(g, red, rows, cols, strata, P.rx, P.ry, Zc);
+        else part32 += g2_partial<float>(g, red, rows, cols, strata, P.rx, P.ry, Zc);
         tab = red;
-        if (c + 1 < P.nchunks) __syncthreads();
+        if (c + 1 < P.nchunks) g.sync();
     }
     *tab_out = tab;
-    const Real s = wg_sum(part, t);
-    return 2.0 * (double)s;
+    if (fp64) return 2.0 * g.sum(part64, t);
+    return 2.0 * (double)g.sum(part32, t);
 }
 
-// FP64 G^2 from a table and marginals still resident in LDS.
-__device__ inline double g2_fp64_resident(TestSh &t, const Plan &P, const uint32_t *tab) {
+// FP64 G^2 from a single-pass table and marginals still resident in LDS.
+BNS_INLINE double g2_fp64_resident(const Grp &g, TestSh &t, const Plan &P, const uint32_t *tab) {
     const uint32_t Zc = P.nstrata;
     const uint32_t *rows = tab + P.rxy * Zc;
     const uint32_t *cols = rows + P.rx * Zc;
     const uint32_t *strata = cols + P.ry * Zc;
-    const double part = g2_partial<double>(tab, rows, cols, strata, P.rx, P.ry, Zc);
-    return 2.0 * wg_sum(part, t);
+    const double part = g2_partial<double>(g, tab, rows, cols, strata, P.rx, P.ry, Zc);
+    return 2.0 * g.sum(part, t);
 }
 
 // Relative error bound of the FP32 G^2 sum: every summand is non-negative and
-// carries a few ulp of error, and each thread adds up to ceil(cells/256) of
-// them before a 256-way tree, so the relative error stays below
-// (8 + cells/256 + 8) * 2^-24 < 1e-5 for tables up to 2^14 cells per pass.
-__device__ inline double fp32_g2_rel_bound(const Plan &P) {
-    const double per_thread = (double)(P.rxy * P.zc_per) / (double)kWG + 1.0;
-    return (16.0 + per_thread) * 5.96e-8 * (double)P.nchunks + 1e-6;
+// carries a few ulp of error, and each lane adds up to ceil(cells/lanes) of
+// them before a tree, so the relative error stays below
+// (16 + cells/lanes) * 2^-24 per pass.
+BNS_INLINE double fp32_g2_rel_bound(const Plan &P, int S) {
+    const double per_lane = (double)(P.rxy * P.zc_per) / (double)S + 1.0;
+    return (16.0 + per_lane) * 5.96e-8 * (double)P.nchunks + 1e-6;
 }
 
-// Runs one complete test with the description in t (all threads of the
-// workgroup, uniform control flow).  alpha drives the decision; gtab (may be
-// null) receives the exact table.
-__device__ inline TestOut run_test(TestSh &t, uint32_t *lds, const Tile &tile, double alpha,
-                                   uint32_t *gtab) {
+// Tail of the group (chi2_tail_wave needs a whole wave; a workgroup lets its
+// first wave evaluate it and broadcasts).
+BNS_INLINE Tail group_tail(const Grp &g, int64_t df, double g2, TestSh &t) {
+    if (!g.block) return chi2_tail_wave(df, g2);
+    Tail r;
+    r.p = 0.0;
+    r.dens = 0.0;
+    if (threadIdx.x < 64) r = chi2_tail_wave(df, g2);
+    if (threadIdx.x == 0) {
+        t.bcast_d[0] = r.p;
+        t.bcast_d[1] = r.dens;
+    }
+    __syncthreads();
+    r.p = t.bcast_d[0];
+    r.dens = t.bcast_d[1];
+    __syncthreads();
+    return r;
+}
+
+// Runs one complete test with the description in t (all lanes of the group,
+// uniform control flow) in W words of LDS at lds.  alpha drives the decision;
+// gtab (may be null) receives the exact table.
+BNS_INLINE TestOut run_test(const Grp &g, TestSh &t, uint32_t *lds, uint32_t W, const Tile &tile,
+                            double alpha, uint32_t *gtab) {
     TestOut o;
     o.flags = 0;
-    const Plan P = make_plan(t, tile);
+    const Plan P = make_plan(t, W, tile.max_rep_log2, g.size);
     o.err = P.err;
     o.df = P.df;
     if (P.err != kDevOk) {
@@ -463,39 +640,29 @@ __device__ inline TestOut run_test(TestSh &t, uint32_t *lds, const Tile &tile, d
         o.p = 1.0;
         return o;
     }
+    // One counting pass in the requested precision; an FP32 decision close to
+    // alpha is re-evaluated in FP64, from the resident table when the test
+    // fitted in one pass, otherwise by a second counting pass.
     const uint32_t *tab = nullptr;
-    double g2 = tile.fp64 ? table_pass<double>(t, P, lds, gtab, &tab)
-                          : table_pass<float>(t, P, lds, gtab, &tab);
-    // The chi-square tail is evaluated by one lane and broadcast.
-    if (threadIdx.x == 0) {
-        double p = chi2_upper(P.df, g2);
-        int recheck = 0;
-        if (!tile.fp64 && P.df > 0) {
-            const double gap = fabs(p - alpha);
-            const double a = 0.5 * (double)P.df, x = 0.5 * g2;
-            const double dp = gamma_density(a, x) * x * fp32_g2_rel_bound(P);
-            recheck = (gap < tile.band) || (gap < 4.0 * dp);
-        }
-        t.bcast_d[0] = p;
-        t.bcast_i[0] = recheck;
-    }
-    __syncthreads();
-    double p = t.bcast_d[0];
-    const int recheck = t.bcast_i[0];
-    __syncthreads();
-    if (recheck) {
-        // FP64 re-evaluation: from the resident table when the test fitted in
-        // one pass, otherwise by recounting.
-        if (P.nchunks == 1) {
-            g2 = g2_fp64_resident(t, P, tab);
-        } else {
-            g2 = table_pass<double>(t, P, lds, nullptr, &tab);
-        }
-        if (threadIdx.x == 0) t.bcast_d[1] = chi2_upper(P.df, g2);
-        __syncthreads();
-        p = t.bcast_d[1];
-        __syncthreads();
+    bool fp64 = tile.fp64 != 0;
+    double g2 = 0.0, p = 1.0;
+    for (int round = 0; round < 2; ++round) {
+        g2 = table_pass(g, t, P, lds, round == 0 ? gtab : nullptr, fp64, &tab);
+        Tail tl = group_tail(g, P.df, g2, t);
+        p = tl.p;
+        if (fp64 || P.df <= 0) break;
+        const double gap = fabs(p - alpha);
+        // propagate the FP32 error bound of G^2 through the tail's slope
+        const double dp = tl.dens * 0.5 * g2 * fp32_g2_rel_bound(P, g.size);
+        if (!(gap < tile.band || gap < 4.0 * dp)) break;
         o.flags |= 2;
+        if (P.nchunks > 1) {
+            fp64 = true;
+            continue;
+        }
+        g2 = g2_fp64_resident(g, t, P, tab);
+        p = group_tail(g, P.df, g2, t).p;
+        break;
     }
     o.g2 = g2;
     o.p = p;

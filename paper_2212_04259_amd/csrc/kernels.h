@@ -26,11 +26,13 @@ struct DepthArgs {
     EdgeRec *edges_tmp;
     EdgeRec *edges;           // sorted by levels, descending
     unsigned long long *min_accept;
-    int32_t *rdepth;          // per pair (problem block), removal depth or -1
-    int64_t *sepoff;          // per pair, offset in pool or -1
-    int32_t *pool;            // sepset members
+    int8_t *rdepth;           // per pair (problem block), removal depth or -1
+    int32_t *pool;            // removal records of depth >= 1: problem, i, j, sepset
     Ctl *ctl;
     Tile tile;
+    int64_t n_pairs;          // variable pairs over all problems
+    int32_t test_waves;       // waves of the persistent test grid
+    int32_t edge_grid;        // workgroups of the per-edge kernels (scatter, removal)
 };
 
 hipError_t launch_depth_prepare(const DepthArgs &a, hipStream_t s);   // snapshot .. scatter

@@ -38,38 +38,10 @@ __device__ inline void unrank_serial(const uint64_t *B, int rows, int64_t p, int
     }
 }
 
-// The same search with the 64 lanes of a wave testing 64 candidate positions
-// at once; every lane returns the same c[0..d) (written by lane 0 into c).
-__device__ inline void unrank_wave(const uint64_t *B, int rows, int64_t p, int d, uint64_t rr,
-                                   int32_t *c) {
-    const int lane = threadIdx.x & 63;
-    int64_t x0 = 0;
-    for (int k = 0; k < d; ++k) {
-        const int j = d - k - 1;
-        const int64_t xmax = p - j - 1;
-        const uint64_t base = binom_at(B, rows, p - x0, j + 1);
-        int64_t ck = x0;
-        for (int64_t xs = x0;; xs += 64) {
-            const int64_t x = xs + lane;
-            const bool ok = (x <= xmax) && (base - binom_at(B, rows, p - x, j + 1) <= rr);
-            const uint64_t mask = __ballot(ok);
-            const int cnt = __popcll(mask);
-            if (cnt < 64 || xs + 63 >= xmax) {
-                ck = xs + cnt - 1;
-                break;
-            }
-        }
-        if (lane == 0) c[k] = (int32_t)ck;
-        rr -= base - binom_at(B, rows, p - ck, j + 1);
-        x0 = ck + 1;
-    }
-}
-
 __global__ void k_ci_batch(const uint8_t *data, int64_t ld, int64_t m, const uint8_t *cards,
                            const CiTestDev *tests, const int32_t *zpool, int64_t n_tests,
                            double alpha, Tile tile, CiOutDev *out, uint32_t *tables,
                            const int64_t *table_off);
-struct PlainTest;
 __global__ void k_plain_count(const uint8_t *data, int64_t ld, int64_t m, const uint8_t *cards,
                               const PlainTest pt, int64_t spb, uint32_t *partials, int64_t T,
                               int lds_words);
@@ -86,7 +58,6 @@ __global__ void k_init_search(DepthArgs A) {
         const int64_t i = e / P.n, j = e - i * P.n;
         A.adj[P.adj_off + e] = (i != j) ? 1 : 0;
         A.rdepth[P.adj_off + e] = -1;
-        A.sepoff[P.adj_off + e] = -1;
     }
     if (pi == 0 && blockIdx.x == 0) {
         Ctl *c = A.ctl;
@@ -98,6 +69,7 @@ __global__ void k_init_search(DepthArgs A) {
             c->total_tickets = 0;
             c->ticket_ctr = 0;
             c->pool_used = 0;
+            c->apply_done = 0;
         }
         for (int i = threadIdx.x; i < kMaxDepths; i += blockDim.x) {
             DepthStatDev z = {};
@@ -112,11 +84,8 @@ __global__ void k_init_search(DepthArgs A) {
 
 // One wave per variable: freeze a(v) (ascending), its size, and the number of
 // surviving edges (v, u) with u > v.
-__global__ __launch_bounds__(kWG) void k_snapshot(DepthArgs A) {
-    if (A.ctl->done) return;
-    const int g = blockIdx.x * kWaves + (threadIdx.x >> 6);
+BNS_INLINE void snapshot_row(const DepthArgs &A, int g) {
     const int lane = threadIdx.x & 63;
-    if (g >= A.n_globals) return;
     const ProbDev &P = A.probs[A.var2prob[g]];
     const int v = g - P.var_off, n = P.n;
     const uint8_t *row = A.adj + P.adj_off + (int64_t)v * n;
@@ -137,6 +106,12 @@ __global__ __launch_bounds__(kWG) void k_snapshot(DepthArgs A) {
     }
 }
 
+__global__ __launch_bounds__(kWG) void k_snapshot(DepthArgs A) {
+    if (A.ctl->done) return;
+    const int g = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (g < A.n_globals) snapshot_row(A, g);
+}
+
 // Single workgroup: exclusive scan of the per-variable edge counts, reset of
 // the per-depth counters.
 __global__ __launch_bounds__(kWG) void k_scan_rows(DepthArgs A) {
@@ -146,9 +121,15 @@ __global__ __launch_bounds__(kWG) void k_scan_rows(DepthArgs A) {
     const int G = A.n_globals;
     const int seg = (G + kWG - 1) / kWG;
     const int b = threadIdx.x * seg, e = min(G, b + seg);
+    __shared__ int mdeg[kWG];
     int64_t s = 0;
-    for (int i = b; i < e; ++i) s += A.rowcnt[i];
+    int md = 0;
+    for (int i = b; i < e; ++i) {
+        s += A.rowcnt[i];
+        md = max(md, A.deg[i]);
+    }
     part[threadIdx.x] = s;
+    mdeg[threadIdx.x] = md;
     __syncthreads();
     if (threadIdx.x == 0) {
         int64_t acc = 0;
@@ -158,6 +139,9 @@ __global__ __launch_bounds__(kWG) void k_scan_rows(DepthArgs A) {
             acc += v;
         }
         c->n_edges = (unsigned long long)acc;
+        int m2 = 0;
+        for (int i = 0; i < kWG; ++i) m2 = max(m2, mdeg[i]);
+        c->maxdeg = m2;
         c->ticket_ctr = 0;
         c->total_tickets = 0;
         if (c->depth >= kMaxDepths) c->error = kDevDepthTooLarge;
@@ -173,6 +157,71 @@ __global__ __launch_bounds__(kWG) void k_scan_rows(DepthArgs A) {
 
 // One wave per variable v: an edge record for every surviving (v, u > v) with
 // its test counts C(|a(v)|-1, d) + C(|a(u)|-1, d) (one test at depth 0).
+BNS_INLINE void edges_row(const DepthArgs &A, Ctl *c, int g, unsigned int *hist) {
+    const int lane = threadIdx.x & 63;
+    const int pi = A.var2prob[g];
+    const ProbDev &P = A.probs[pi];
+    const int v = g - P.var_off, n = P.n;
+    const int d = c->depth;
+    const bool depth_ok = (P.max_depth < 0 || d <= P.max_depth);
+    const uint8_t *row = A.adj + P.adj_off + (int64_t)v * n;
+    const int dv = A.deg[g];
+    const int64_t base = A.rowbase[g];
+    const uint64_t lt = lanes_below_mask();
+    int cnt = 0, hi = 0;
+    for (int u0 = 0; u0 < n; u0 += 64) {
+        const int u = u0 + lane;
+        const bool a = (u < n) && row[u];
+        const uint64_t mask = __ballot(a);
+        const bool take = a && u > v;
+        const uint64_t mhi = __ballot(take);
+        if (take) {
+            EdgeRec e;
+            e.prob = pi;
+            e.i = v;
+            e.j = u;
+            e.posj = cnt + __popcll(mask & lt);
+            const int du = A.deg[P.var_off + u];
+            uint64_t nA = 0, nB = 0;
+            if (depth_ok) {
+                if (d == 0) {
+                    nA = 1;
+                } else if (d > kMaxZ) {
+                    if (dv - 1 >= d || du - 1 >= d) c->error = kDevDepthTooLarge;
+                } else {
+                    nA = binom_at(A.binom, A.binom_rows, dv - 1, d);
+                    nB = binom_at(A.binom, A.binom_rows, du - 1, d);
+                }
+            }
+            uint64_t ntot = nA + nB;
+            if (ntot > (1ull << 40)) {
+                c->error = kDevTooManyTests;
+                nA = nB = ntot = 0;
+            }
+            e.nA = nA;
+            e.n = ntot;
+            e.pA = dv - 1;
+            e.pB = du - 1;
+            e.posi = 0;
+            if (nB > 0) {
+                // position of v in the ascending list a(u)
+                const int32_t *nbu = A.nbr + P.adj_off + (int64_t)u * n;
+                int lo = 0, hi2 = du;
+                while (lo < hi2) {
+                    const int mid = (lo + hi2) >> 1;
+                    if (nbu[mid] < v) lo = mid + 1; else hi2 = mid;
+                }
+                e.posi = lo;
+            }
+            e.levels = ntot ? 64 - __clzll(ntot) : 0;
+            atomicAdd(&hist[e.levels], 1u);
+            A.edges_tmp[base + hi + __popcll(mhi & lt)] = e;
+        }
+        cnt += __popcll(mask);
+        hi += __popcll(mhi);
+    }
+}
+
 __global__ __launch_bounds__(kWG) void k_edges(DepthArgs A) {
     __shared__ unsigned int hist[kMaxLevels + 2];
     Ctl *c = A.ctl;
@@ -180,251 +229,412 @@ __global__ __launch_bounds__(kWG) void k_edges(DepthArgs A) {
     for (int i = threadIdx.x; i < kMaxLevels + 2; i += kWG) hist[i] = 0;
     __syncthreads();
     const int g = blockIdx.x * kWaves + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (live && g < A.n_globals && A.rowcnt[g] > 0) {
-        const int pi = A.var2prob[g];
-        const ProbDev &P = A.probs[pi];
-        const int v = g - P.var_off, n = P.n;
-        const int d = c->depth;
-        const bool depth_ok = (P.max_depth < 0 || d <= P.max_depth);
-        const uint8_t *row = A.adj + P.adj_off + (int64_t)v * n;
-        const int dv = A.deg[g];
-        const int64_t base = A.rowbase[g];
-        const uint64_t lt = lanes_below_mask();
-        int cnt = 0, hi = 0;
-        for (int u0 = 0; u0 < n; u0 += 64) {
-            const int u = u0 + lane;
-            const bool a = (u < n) && row[u];
-            const uint64_t mask = __ballot(a);
-            const bool take = a && u > v;
-            const uint64_t mhi = __ballot(take);
-            if (take) {
-                EdgeRec e;
-                e.prob = pi;
-                e.i = v;
-                e.j = u;
-                e.posj = cnt + __popcll(mask & lt);
-                const int du = A.deg[P.var_off + u];
-                uint64_t nA = 0, nB = 0;
-                if (depth_ok) {
-                    if (d == 0) {
-                        nA = 1;
-                    } else if (d > kMaxZ) {
-                        if (dv - 1 >= d || du - 1 >= d) c->error = kDevDepthTooLarge;
-                    } else {
-                        nA = binom_at(A.binom, A.binom_rows, dv - 1, d);
-                        nB = binom_at(A.binom, A.binom_rows, du - 1, d);
-                    }
-                }
-                uint64_t ntot = nA + nB;
-                if (ntot > (1ull << 40)) {
-                    c->error = kDevTooManyTests;
-                    nA = nB = ntot = 0;
-                }
-                e.nA = nA;
-                e.n = ntot;
-                e.posi = 0;
-                if (nB > 0) {
-                    // position of v in the ascending list a(u)
-                    const int32_t *nbu = A.nbr + P.adj_off + (int64_t)u * n;
-                    int lo = 0, hi2 = du;
-                    while (lo < hi2) {
-                        const int mid = (lo + hi2) >> 1;
-                        if (nbu[mid] < v) lo = mid + 1; else hi2 = mid;
-                    }
-                    e.posi = lo;
-                }
-                e.levels = ntot ? 64 - __clzll(ntot) : 0;
-                atomicAdd(&hist[e.levels], 1u);
-                A.edges_tmp[base + hi + __popcll(mhi & lt)] = e;
-            }
-            cnt += __popcll(mask);
-            hi += __popcll(mhi);
-        }
-    }
+    if (live && g < A.n_globals && A.rowcnt[g] > 0) edges_row(A, c, g, hist);
     __syncthreads();
     for (int i = threadIdx.x; i < kMaxLevels + 2; i += kWG)
         if (hist[i]) atomicAdd(&c->hist[i], hist[i]);
 }
 
-// Single thread: ticket levels.  Edges are ordered by their number of levels,
+// One wave: ticket levels.  Edges are ordered by their number of levels,
 // descending, so the edges with a test of rank r form a prefix; level L holds
 // ranks [2^L - 1, 2^(L+1) - 1) of the first level_cnt[L] edges, rank-major.
-__global__ void k_levels(DepthArgs A) {
-    Ctl *c = A.ctl;
-    if (threadIdx.x != 0 || c->done) return;
-    unsigned int acc = 0;
-    for (int lv = kMaxLevels + 1; lv >= 0; --lv) {
-        c->cursor[lv] = acc;
-        acc += c->hist[lv];
+BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist) {
+    const int lane = threadIdx.x & 63;
+    // cursor[lv] = number of edges with more than lv levels (bucket start in
+    // the descending order); lanes hold lv = lane and lv = 64, 65 go to lane 0.
+    const unsigned int h = hist[lane];
+    unsigned int suf = h;  // inclusive suffix sum over lanes >= lane
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned int o = __shfl_down(suf, off, 64);
+        if (lane + off < 64) suf += o;
     }
-    unsigned long long base = 0;
-    for (int L = 0; L <= kMaxLevels; ++L) {
-        const unsigned long long cnt = (L < kMaxLevels) ? c->cursor[L] : 0ull;
-        c->level_base[L] = base;
-        c->level_cnt[L] = cnt;
-        if (cnt) {
-            if (L >= 60 || cnt > ((1ull << 61) >> L)) {
-                c->error = kDevTooManyTests;
-                break;
-            }
-            base += cnt << L;
+    const unsigned int hi = hist[kMaxLevels] + hist[kMaxLevels + 1];
+    const unsigned int start = suf - h + hi;  // edges with levels > lane
+    c->cursor[lane] = start;
+    if (lane == 0) {
+        c->cursor[kMaxLevels + 1] = 0;
+        c->cursor[kMaxLevels] = hist[kMaxLevels + 1];
+    }
+    // level L (= lane): cnt = edges with levels > L, tickets cnt * 2^L
+    const unsigned long long cnt = start;
+    int bad = 0;
+    unsigned long long tk = 0;
+    if (cnt) {
+        if (lane >= 60 || cnt > ((1ull << 61) >> lane)) bad = 1;
+        else tk = cnt << lane;
+    }
+    unsigned long long pre = tk;  // inclusive prefix over lanes <= lane
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned long long o = __shfl_up(pre, off, 64);
+        if (lane >= off) pre += o;
+    }
+    c->level_base[lane] = pre - tk;
+    c->level_cnt[lane] = cnt;
+    const unsigned long long total = __shfl(pre, 63, 64);
+    const bool any_bad = __ballot(bad) != 0ull;
+    if (lane == 0) {
+        c->level_base[kMaxLevels] = total;
+        c->level_cnt[kMaxLevels] = 0;
+        const int d = c->depth;
+        if (any_bad) c->error = kDevTooManyTests;
+        c->total_tickets = any_bad ? 0ull : total;
+        c->ticket_ctr = 0;
+        // Few tickets: a workgroup per test (shorter tests, less speculation);
+        // otherwise a wave per test.  Grabs of several tickets amortise the
+        // decode latency when there is work for several rounds.
+        const unsigned long long tw = (unsigned long long)max(A.test_waves, 1);
+        if (total < 8ull * tw) {
+            c->mode = 1;
+            const unsigned long long per = total / (4ull * (tw / kWaves + 1));
+            c->batch = (int)max(1ull, min(per, (unsigned long long)kSlotsPerWave));
+        } else {
+            c->mode = 0;
+            const unsigned long long per = total / (4ull * tw);
+            c->batch = (int)max(1ull, min(per, (unsigned long long)kSlotsPerWave));
         }
-    }
-    const int d = c->depth;
-    c->total_tickets = base;
-    c->ticket_ctr = 0;
-    if (base == 0) {
-        c->done = 1;
-    } else if (d < kMaxDepths) {
-        c->stats[d].edges = c->n_edges;
-        c->stats[d].tickets = base;
+        if (total == 0 || any_bad) {
+            c->done = 1;
+        } else if (d < kMaxDepths) {
+            c->stats[d].edges = c->n_edges;
+            c->stats[d].tickets = total;
+        }
     }
 }
 
-// Scatter into level order and reset the per-edge first-accept ranks.
+__global__ void k_levels(DepthArgs A) {
+    Ctl *c = A.ctl;
+    if (c->done) return;
+    levels_wave(A, c, c->hist);
+}
+
+// Scatter into level order and reset the per-edge first-accept ranks.  The
+// bucket cursors are bumped once per distinct level value per wave.
+BNS_INLINE void scatter_edges(const DepthArgs &A, Ctl *c, unsigned long long first,
+                              unsigned long long stride) {
+    const unsigned long long E = c->n_edges;
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = lanes_below_mask();
+    for (unsigned long long base = first; base < E; base += stride) {
+        const unsigned long long e = base + lane;
+        const bool valid = e < E;
+        EdgeRec r;
+        int lv = -1;
+        if (valid) {
+            r = A.edges_tmp[e];
+            lv = r.levels;
+        }
+        uint64_t todo = __ballot(valid);
+        unsigned int pos = 0;
+        while (todo) {
+            const int leader = __ffsll((long long)todo) - 1;
+            const int L = __shfl(lv, leader, 64);
+            const uint64_t same = __ballot(valid && lv == L);
+            unsigned int b = 0;
+            if (lane == leader) b = atomicAdd(&c->cursor[L], (unsigned int)__popcll(same));
+            b = __shfl(b, leader, 64);
+            if (valid && lv == L) pos = b + (unsigned int)__popcll(same & lt);
+            todo &= ~same;
+        }
+        if (valid) {
+            A.edges[pos] = r;
+            A.min_accept[pos] = ~0ull;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kWG) void k_scatter(DepthArgs A) {
     Ctl *c = A.ctl;
     if (c->done) return;
-    const unsigned long long E = c->n_edges;
-    for (unsigned long long e = (unsigned long long)blockIdx.x * kWG + threadIdx.x; e < E;
-         e += (unsigned long long)gridDim.x * kWG) {
-        const EdgeRec r = A.edges_tmp[e];
-        const unsigned int pos = atomicAdd(&c->cursor[r.levels], 1u);
-        A.edges[pos] = r;
-        A.min_accept[pos] = ~0ull;
+    scatter_edges(A, c, (unsigned long long)blockIdx.x * kWG + (threadIdx.x & ~63u),
+                  (unsigned long long)gridDim.x * kWG);
+}
+
+// All preparation steps of a depth in one workgroup, for searches with at
+// most kSmallRows variables and kSmallPairs pairs: frozen adjacency lists,
+// edge records, ticket levels and level order.
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallRows = 1024;
+constexpr int64_t kSmallPairs = 65536;
+
+__global__ __launch_bounds__(kSmallThreads) void k_prepare_small(DepthArgs A) {
+    Ctl *c = A.ctl;
+    if (c->done) return;
+    __shared__ unsigned int hist[kMaxLevels + 2];
+    __shared__ int64_t wsum[kSmallThreads / 64];
+    __shared__ int wmax[kSmallThreads / 64];
+    const int nw = kSmallThreads / 64, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int G = A.n_globals;
+    for (int i = threadIdx.x; i < kMaxLevels + 2; i += kSmallThreads) hist[i] = 0;
+    for (int g = w; g < G; g += nw) snapshot_row(A, g);
+    __syncthreads();
+    // exclusive scan of the per-variable edge counts (one variable per thread)
+    const int g0 = threadIdx.x;
+    const int64_t mine = (g0 < G) ? A.rowcnt[g0] : 0;
+    const int md = (g0 < G) ? A.deg[g0] : 0;
+    int64_t inc = mine;
+    int mx = md;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t o = __shfl_up(inc, off, 64);
+        const int om = __shfl_xor(mx, off, 64);
+        if (lane >= off) inc += o;
+        mx = max(mx, om);
     }
+    if (lane == 63) wsum[w] = inc;
+    if (lane == 0) wmax[w] = mx;
+    __syncthreads();
+    int64_t before = 0, total = 0;
+    int maxdeg = 0;
+    for (int i = 0; i < nw; ++i) {
+        if (i < w) before += wsum[i];
+        total += wsum[i];
+        maxdeg = max(maxdeg, wmax[i]);
+    }
+    if (g0 < G) A.rowbase[g0] = before + inc - mine;
+    if (threadIdx.x == 0) {
+        c->n_edges = (unsigned long long)total;
+        c->maxdeg = maxdeg;
+        c->ticket_ctr = 0;
+        c->total_tickets = 0;
+        if (c->depth >= kMaxDepths) c->error = kDevDepthTooLarge;
+    }
+    __syncthreads();
+    for (int g = w; g < G; g += nw)
+        if (A.rowcnt[g] > 0) edges_row(A, c, g, hist);
+    __syncthreads();
+    if (w == 0) levels_wave(A, c, hist);
+    __syncthreads();
+    if (c->done) return;
+    scatter_edges(A, c, (unsigned long long)w * 64, (unsigned long long)kSmallThreads);
 }
 
 // ---------------------------------------------------------------------------
 // Persistent per-depth test kernel.
 //
-// Workgroups take tickets from one counter.  A ticket names (edge, rank r);
-// the conditioning set is unranked on the fly from r (Section IV-C) over the
+// Tickets come from one counter.  A ticket names (edge, rank r); the
+// conditioning set is unranked on the fly from r (Section IV-C) over the
 // frozen adjacency list of side A (lower id) for r < nA, else side B.  A test
 // whose rank exceeds the smallest accepting rank already found for its edge
 // is skipped; since every rank below the final smallest accepting rank is
 // always run, the edge's first accepting set in the sequential order is found
 // exactly, whatever the interleaving.
+//
+// Tickets are taken `batch` at a time and decoded lane-parallel into LDS
+// descriptors (one lane per ticket), so the dependent loads of a ticket
+// (edge record, neighbour lists, cardinalities) cost one latency chain per
+// batch.  Mode 0 runs one test per wave in a quarter of the workgroup's LDS;
+// mode 1 runs one test per workgroup in all of it.
 // ---------------------------------------------------------------------------
-struct TicketSh {
-    unsigned long long level_base[kMaxLevels + 1];
-    unsigned long long level_cnt[kMaxLevels + 1];
-    unsigned long long ticket;
+struct Desc {
+    const uint8_t *data;
+    int64_t ld;
+    int64_t m;
+    double alpha;
     unsigned long long r;
-    int64_t edge;
-    int32_t go;
-    int32_t nlev;
-    int32_t pos[kMaxZ];
+    int64_t e;
+    int32_t valid;
+    int32_t ncols;
+    int32_t var[kMaxCols];
+    uint8_t card[kMaxCols];
 };
 
-__global__ __launch_bounds__(kWG) void k_depth_tests(DepthArgs A) {
+constexpr int kBinomLds = 512;  // binomial entries staged in LDS
+
+BNS_INLINE uint64_t bnm(const uint64_t *tab, int stride, int rows, int64_t n, int k) {
+    if (n < 0 || k < 0 || k > n) return 0;
+    if (n >= rows) return ~0ull >> 2;
+    return tab[n * stride + k];
+}
+
+// Lexicographic unranking by one lane: position c_k of the rank-rr size-d
+// subset of {0..p-1}; S(x) = C(p - x0, j + 1) - C(p - x, j + 1) counts the
+// subsets with the current prefix whose next element is below x
+// (hockey-stick identity).  Writes the positions to out[0..d).
+BNS_INLINE void unrank_lane(const uint64_t *tab, int stride, int rows, int64_t p, int d,
+                            uint64_t rr, int32_t *out) {
+    int64_t x0 = 0;
+    for (int k = 0; k < d; ++k) {
+        const int j = d - k - 1;
+        const uint64_t base = bnm(tab, stride, rows, p - x0, j + 1);
+        int64_t x = x0;
+        while (x + 1 <= p - j - 1 && base - bnm(tab, stride, rows, p - (x + 1), j + 1) <= rr) ++x;
+        out[k] = (int32_t)x;
+        rr -= base - bnm(tab, stride, rows, p - x, j + 1);
+        x0 = x + 1;
+    }
+}
+
+BNS_INLINE void decode_ticket(const DepthArgs &A, const unsigned long long *lvl_base,
+                              const unsigned long long *lvl_cnt, int nlev, unsigned long long tk,
+                              int d, const uint64_t *btab, int bstride, int brows, Desc &q) {
+    int lo = 0, hi = nlev - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (lvl_base[mid] <= tk) lo = mid;
+        else hi = mid - 1;
+    }
+    const int L = lo;
+    const unsigned long long off = tk - lvl_base[L];
+    const unsigned long long cnt = lvl_cnt[L];
+    const unsigned long long jj = off / cnt;
+    const int64_t e = (int64_t)(off - jj * cnt);
+    const unsigned long long r = ((1ull << L) - 1ull) + jj;
+    const EdgeRec rec = A.edges[e];
+    const unsigned long long ma =
+        __hip_atomic_load(&A.min_accept[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    q.valid = (r < rec.n && r <= ma) ? 1 : 0;
+    if (!q.valid) return;
+    const ProbDev P = A.probs[rec.prob];
+    q.data = P.data;
+    q.ld = P.ld;
+    q.m = P.m;
+    q.alpha = P.alpha;
+    q.r = r;
+    q.e = e;
+    q.ncols = d + 2;
+    q.var[0] = rec.i;
+    q.var[1] = rec.j;
+    if (d > 0) {
+        const bool sideA = r < rec.nA;
+        const int owner = sideA ? rec.i : rec.j;
+        const int skip = sideA ? rec.posj : rec.posi;
+        const int64_t p = sideA ? rec.pA : rec.pB;
+        unrank_lane(btab, bstride, brows, p, d, sideA ? r : r - rec.nA, q.var + 2);
+        const int32_t *nbo = A.nbr + P.adj_off + (int64_t)owner * P.n;
+        int32_t vv[kMaxZ];
+#pragma unroll
+        for (int k = 0; k < kMaxZ; ++k)
+            if (k < d) {
+                const int pos = q.var[2 + k];
+                vv[k] = nbo[pos + (pos >= skip ? 1 : 0)];
+            }
+#pragma unroll
+        for (int k = 0; k < kMaxZ; ++k)
+            if (k < d) q.var[2 + k] = vv[k];
+    }
+    uint8_t cc[kMaxCols];
+#pragma unroll
+    for (int k = 0; k < kMaxCols; ++k)
+        if (k < d + 2) cc[k] = A.cards[P.var_off + q.var[k]];
+#pragma unroll
+    for (int k = 0; k < kMaxCols; ++k)
+        if (k < d + 2) q.card[k] = cc[k];
+}
+
+// Stages a decoded test into the group's TestSh (all lanes of the group).
+BNS_INLINE void stage_test(const Grp &g, const Desc &q, TestSh &t) {
+    for (int k = g.rank; k < q.ncols; k += g.size) {
+        t.col[k] = q.data + (int64_t)q.var[k] * q.ld;
+        t.card[k] = q.card[k];
+    }
+    if (g.rank == 0) {
+        t.ncols = q.ncols;
+        t.m = q.m;
+        uint32_t mlt = 1;
+        for (int k = 0; k < q.ncols; ++k) {
+            t.mult[k] = mlt;
+            mlt *= q.card[k];
+        }
+    }
+    g.sync();
+}
+
+BNS_INLINE unsigned long long bcast_u64(unsigned long long v) {
+    const unsigned lo = __shfl((unsigned)(v & 0xffffffffull), 0, 64);
+    const unsigned hi = __shfl((unsigned)(v >> 32), 0, 64);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k_depth_tests(DepthArgs A) {
     extern __shared__ uint32_t lds[];
-    __shared__ TestSh t;
-    __shared__ TicketSh ts;
+    __shared__ TestSh tsh[kWaves];
+    __shared__ Desc slots[kWaves * kSlotsPerWave];
+    __shared__ unsigned long long lvl_base[kMaxLevels + 1];
+    __shared__ unsigned long long lvl_cnt[kMaxLevels + 1];
+    __shared__ uint64_t btab_lds[kBinomLds];
+    __shared__ unsigned long long grab;
     Ctl *c = A.ctl;
     if (c->done || c->error) return;
     const int d = c->depth;
     const unsigned long long total = c->total_tickets;
+    const int mode = c->mode;
+    const int B = c->batch;
     if (threadIdx.x <= kMaxLevels) {
-        ts.level_base[threadIdx.x] = c->level_base[threadIdx.x];
-        ts.level_cnt[threadIdx.x] = c->level_cnt[threadIdx.x];
+        lvl_base[threadIdx.x] = c->level_base[threadIdx.x];
+        lvl_cnt[threadIdx.x] = c->level_cnt[threadIdx.x];
     }
-    if (threadIdx.x == 0) {
-        int nl = 0;
-        while (nl < kMaxLevels && c->level_cnt[nl] > 0) ++nl;
-        ts.nlev = nl;
+    // binomials C(n, k), n <= max degree, k <= d: in LDS when they fit
+    const int brows_need = c->maxdeg + 1;
+    const uint64_t *btab = A.binom;
+    int bstride = kBinomK, brows = A.binom_rows;
+    if (brows_need * (d + 1) <= kBinomLds && brows_need <= A.binom_rows) {
+        for (int i = threadIdx.x; i < brows_need * (d + 1); i += kWG) {
+            const int n = i / (d + 1), k = i - n * (d + 1);
+            btab_lds[i] = A.binom[n * kBinomK + k];
+        }
+        btab = btab_lds;
+        bstride = d + 1;
+        brows = brows_need;
     }
     __syncthreads();
+    int nlev = 0;
+    while (nlev < kMaxLevels && lvl_cnt[nlev] > 0) ++nlev;
+    const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const bool wave0 = threadIdx.x < 64;
     unsigned long long executed = 0, rechecks = 0;
     double bytes = 0.0;
+    // mode 0: one test per wave in a quarter of the LDS; mode 1: one test per
+    // workgroup in all of it
+    const Grp g = mode ? Grp::workgroup() : Grp::wave();
+    TestSh &t = tsh[mode ? 0 : w];
+    Desc *mine = mode ? slots : slots + w * kSlotsPerWave;
+    const uint32_t W = mode ? (uint32_t)A.tile.lds_words : (uint32_t)A.tile.lds_words / kWaves;
+    uint32_t *region = mode ? lds : lds + (uint32_t)w * W;
     for (;;) {
-        if (threadIdx.x == 0) ts.ticket = atomicAdd(&c->ticket_ctr, 1ull);
-        __syncthreads();
-        const unsigned long long tk = ts.ticket;
-        if (tk >= total) break;
-        if (wave0) {
-            // level of the ticket: largest L with level_base[L] <= tk
-            const bool le = lane < ts.nlev && ts.level_base[lane] <= tk;
-            const int L = __popcll(__ballot(le)) - 1;
-            const unsigned long long off = tk - ts.level_base[L];
-            const unsigned long long cnt = ts.level_cnt[L];
-            const unsigned long long jj = off / cnt;
-            const int64_t e = (int64_t)(off - jj * cnt);
-            const unsigned long long r = ((1ull << L) - 1ull) + jj;
-            const EdgeRec rec = A.edges[e];
-            const unsigned long long ma =
-                __hip_atomic_load(&A.min_accept[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const bool go = (r < rec.n) && (r <= ma);
-            if (go) {
-                const ProbDev &P = A.probs[rec.prob];
-                const int n = P.n;
-                const bool sideA = r < rec.nA;
-                const int owner = sideA ? rec.i : rec.j;
-                const int skip = sideA ? rec.posj : rec.posi;
-                const int64_t p = (int64_t)A.deg[P.var_off + owner] - 1;
-                if (d > 0)
-                    unrank_wave(A.binom, A.binom_rows, p, d, sideA ? r : r - rec.nA, ts.pos);
-                // columns: x = V_i, y = V_j, then the conditioning variables
-                const int32_t *nbo = A.nbr + P.adj_off + (int64_t)owner * n;
-                for (int k = lane; k < d + 2; k += 64) {
-                    int var;
-                    if (k == 0) var = rec.i;
-                    else if (k == 1) var = rec.j;
-                    else {
-                        const int q = ts.pos[k - 2];
-                        var = nbo[q + (q >= skip ? 1 : 0)];
-                    }
-                    t.col[k] = P.data + (int64_t)var * P.ld;
-                    t.card[k] = A.cards[P.var_off + var];
-                }
-                if (lane == 0) {
-                    t.ncols = d + 2;
-                    t.m = P.m;
-                    ts.r = r;
-                    ts.edge = e;
-                    t.bcast_d[0] = P.alpha;
-                }
-            }
-            if (lane == 0) ts.go = go ? 1 : 0;
+        unsigned long long base = 0;
+        if (g.rank == 0) base = atomicAdd(&c->ticket_ctr, (unsigned long long)B);
+        if (mode) {
+            if (threadIdx.x == 0) grab = base;
+            __syncthreads();
+            base = grab;
+            __syncthreads();
+        } else {
+            base = bcast_u64(base);
         }
-        __syncthreads();
-        if (ts.go) {
-            if (threadIdx.x == 0) {
-                uint32_t mlt = 1;
-                for (int k = 0; k < t.ncols; ++k) {
-                    t.mult[k] = mlt;
-                    mlt *= t.card[k];
-                }
-            }
-            __syncthreads();
-            const double alpha = t.bcast_d[0];
-            const int64_t e = ts.edge;
-            const unsigned long long r = ts.r;
-            __syncthreads();
-            const TestOut o = run_test(t, lds, A.tile, alpha, nullptr);
-            if (threadIdx.x == 0) {
+        if (base >= total) break;
+        const int cnt = (int)min((unsigned long long)B, total - base);
+        if (g.rank < cnt)
+            decode_ticket(A, lvl_base, lvl_cnt, nlev, base + g.rank, d, btab, bstride, brows,
+                          mine[g.rank]);
+        g.sync();
+        for (int j = 0; j < cnt; ++j) {
+            const Desc &q = mine[j];
+            if (!q.valid) continue;
+            stage_test(g, q, t);
+            const TestOut o = run_test(g, t, region, W, A.tile, q.alpha, nullptr);
+            if (g.rank == 0) {
                 ++executed;
-                bytes += (double)t.ncols * (double)t.m;
+                bytes += (double)q.ncols * (double)q.m;
                 if (o.flags & 2) ++rechecks;
                 if (o.err) c->error = o.err;
-                if (o.flags & 1) atomicMin(&A.min_accept[e], r);
+                if (o.flags & 1) atomicMin(&A.min_accept[q.e], q.r);
             }
+            g.sync();
         }
-        __syncthreads();
     }
-    if (threadIdx.x == 0 && d < kMaxDepths) {
-        atomicAdd(&c->stats[d].executed, executed);
-        atomicAdd(&c->stats[d].rechecks, rechecks);
-        atomicAdd(&c->stats[d].operand_bytes, bytes);
+    if (lane == 0 && d < kMaxDepths) {
+        if (executed) atomicAdd(&c->stats[d].executed, executed);
+        if (rechecks) atomicAdd(&c->stats[d].rechecks, rechecks);
+        if (executed) atomicAdd(&c->stats[d].operand_bytes, bytes);
     }
 }
 
 // ---------------------------------------------------------------------------
 // Depth completion: remove accepted edges, record sepsets and the canonical
 // test count (per edge: ranks up to and including its first accepting one).
+// The last block to finish advances the control block to the next depth.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kWG) void k_apply(DepthArgs A) {
     Ctl *c = A.ctl;
@@ -432,42 +642,59 @@ __global__ __launch_bounds__(kWG) void k_apply(DepthArgs A) {
     __shared__ unsigned long long red[2][kWaves];
     const int d = c->depth;
     const unsigned long long E = c->n_edges;
-    const unsigned long long pool0 = c->pool_used;
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = lanes_below_mask();
     unsigned long long req = 0, rem = 0;
-    for (unsigned long long e = (unsigned long long)blockIdx.x * kWG + threadIdx.x; e < E;
-         e += (unsigned long long)gridDim.x * kWG) {
-        const EdgeRec r = A.edges[e];
-        const unsigned long long ma = A.min_accept[e];
-        if (ma == ~0ull) {
-            req += r.n;
-            continue;
+    // Removal records of depth >= 1 go to the pool, densely:
+    // [problem, i, j, s_1 .. s_d] (d + 3 words), one atomic per wave.
+    for (unsigned long long base = (unsigned long long)blockIdx.x * kWG + (threadIdx.x & ~63u);
+         base < E; base += (unsigned long long)gridDim.x * kWG) {
+        const unsigned long long e = base + lane;
+        const bool valid = e < E;
+        EdgeRec r;
+        unsigned long long ma = ~0ull;
+        if (valid) {
+            r = A.edges[e];
+            ma = A.min_accept[e];
+            req += (ma == ~0ull) ? r.n : ma + 1;
         }
-        req += ma + 1;
-        ++rem;
+        const bool removed = valid && ma != ~0ull;
+        const uint64_t rmask = __ballot(removed);
+        if (rmask == 0ull) continue;
+        rem += removed ? 1 : 0;
+        unsigned long long off = 0;
+        if (d > 0) {
+            const unsigned long long rec = (unsigned long long)(d + 3);
+            unsigned long long b0 = 0;
+            if (lane == 0) b0 = atomicAdd(&c->pool_used, rec * (unsigned long long)__popcll(rmask));
+            b0 = __shfl(b0, 0, 64);
+            off = b0 + rec * (unsigned long long)__popcll(rmask & lt);
+        }
+        if (!removed) continue;
         const ProbDev &P = A.probs[r.prob];
         const int n = P.n;
-        const unsigned long long off = pool0 + e * (unsigned long long)d;
         if (d > 0) {
             int32_t cpos[kMaxZ];
             const bool sideA = ma < r.nA;
             const int owner = sideA ? r.i : r.j;
             const int skip = sideA ? r.posj : r.posi;
-            const int64_t p = (int64_t)A.deg[P.var_off + owner] - 1;
+            const int64_t p = sideA ? r.pA : r.pB;
             unrank_serial(A.binom, A.binom_rows, p, d, sideA ? ma : ma - r.nA, cpos);
             const int32_t *nbo = A.nbr + P.adj_off + (int64_t)owner * n;
+            A.pool[off] = r.prob;
+            A.pool[off + 1] = r.i;
+            A.pool[off + 2] = r.j;
             for (int k = 0; k < d; ++k) {
                 const int q = cpos[k];
-                A.pool[off + k] = nbo[q + (q >= skip ? 1 : 0)];
+                A.pool[off + 3 + k] = nbo[q + (q >= skip ? 1 : 0)];
             }
         }
         const int64_t ij = P.adj_off + (int64_t)r.i * n + r.j;
         const int64_t ji = P.adj_off + (int64_t)r.j * n + r.i;
         A.adj[ij] = 0;
         A.adj[ji] = 0;
-        A.rdepth[ij] = d;
-        A.rdepth[ji] = d;
-        A.sepoff[ij] = (int64_t)off;
-        A.sepoff[ji] = (int64_t)off;
+        A.rdepth[ij] = (int8_t)d;
+        A.rdepth[ji] = (int8_t)d;
     }
     req = wave_sum(req);
     rem = wave_sum(rem);
@@ -476,22 +703,24 @@ __global__ __launch_bounds__(kWG) void k_apply(DepthArgs A) {
         red[1][threadIdx.x >> 6] = rem;
     }
     __syncthreads();
-    if (threadIdx.x == 0 && d < kMaxDepths) {
+    if (threadIdx.x == 0) {
         unsigned long long a = 0, b = 0;
         for (int w = 0; w < kWaves; ++w) {
             a += red[0][w];
             b += red[1][w];
         }
-        if (a) atomicAdd(&c->stats[d].required, a);
-        if (b) atomicAdd(&c->stats[d].removed, b);
+        if (d < kMaxDepths) {
+            if (a) atomicAdd(&c->stats[d].required, a);
+            if (b) atomicAdd(&c->stats[d].removed, b);
+        }
+        __threadfence();
+        const unsigned int fin = atomicAdd(&c->apply_done, 1u);
+        if (fin == gridDim.x - 1) {
+            // every block has read the depth: advance to the next one
+            c->depth = d + 1;
+            c->apply_done = 0;
+        }
     }
-}
-
-__global__ void k_finish_depth(DepthArgs A) {
-    Ctl *c = A.ctl;
-    if (threadIdx.x != 0 || c->done) return;
-    c->pool_used += c->n_edges * (unsigned long long)c->depth;
-    c->depth += 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -505,12 +734,16 @@ hipError_t launch_init_search(const DepthArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_depth_prepare(const DepthArgs &a, hipStream_t s) {
+    if (a.n_globals <= kSmallRows && a.n_pairs <= kSmallPairs) {
+        hipLaunchKernelGGL(k_prepare_small, dim3(1), dim3(kSmallThreads), 0, s, a);
+        return hipGetLastError();
+    }
     const int gr = grid_rows(a.n_globals);
     hipLaunchKernelGGL(k_snapshot, dim3(gr), dim3(kWG), 0, s, a);
     hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(kWG), 0, s, a);
     hipLaunchKernelGGL(k_edges, dim3(gr), dim3(kWG), 0, s, a);
     hipLaunchKernelGGL(k_levels, dim3(1), dim3(64), 0, s, a);
-    hipLaunchKernelGGL(k_scatter, dim3(1024), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL(k_scatter, dim3(a.edge_grid), dim3(kWG), 0, s, a);
     return hipGetLastError();
 }
 
@@ -520,8 +753,7 @@ hipError_t launch_depth_tests(const DepthArgs &a, int grid, hipStream_t s) {
 }
 
 hipError_t launch_depth_apply(const DepthArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_apply, dim3(1024), dim3(kWG), 0, s, a);
-    hipLaunchKernelGGL(k_finish_depth, dim3(1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_apply, dim3(a.edge_grid), dim3(kWG), 0, s, a);
     return hipGetLastError();
 }
 
@@ -546,7 +778,8 @@ int depth_tests_max_wg_per_cu(int lds_bytes) {
 }
 
 // ---------------------------------------------------------------------------
-// Batched CI tests (bns_ci_batch)
+// Batched CI tests (bns_ci_batch): one test per wave, same device path as the
+// skeleton search.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kWG) void k_ci_batch(const uint8_t *data, int64_t ld, int64_t m,
                                                   const uint8_t *cards, const CiTestDev *tests,
@@ -554,17 +787,23 @@ __global__ __launch_bounds__(kWG) void k_ci_batch(const uint8_t *data, int64_t l
                                                   double alpha, Tile tile, CiOutDev *out,
                                                   uint32_t *tables, const int64_t *table_off) {
     extern __shared__ uint32_t lds[];
-    __shared__ TestSh t;
-    for (int64_t ti = blockIdx.x; ti < n_tests; ti += gridDim.x) {
+    __shared__ TestSh tsh[kWaves];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    TestSh &t = tsh[w];
+    const Grp gw = Grp::wave();
+    const uint32_t W = (uint32_t)tile.lds_words / kWaves;
+    uint32_t *region = lds + (uint32_t)w * W;
+    for (int64_t ti = (int64_t)blockIdx.x * kWaves + w; ti < n_tests;
+         ti += (int64_t)gridDim.x * kWaves) {
         const CiTestDev q = tests[ti];
-        if (threadIdx.x < q.nz + 2) {
-            const int k = threadIdx.x;
+        for (int k = lane; k < q.nz + 2; k += 64) {
             const int var = (k == 0) ? q.x : (k == 1) ? q.y : zpool[q.zoff + k - 2];
             t.col[k] = data + (int64_t)var * ld;
             t.card[k] = cards[var];
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
+        gw.sync();
+        if (lane == 0) {
             t.ncols = q.nz + 2;
             t.m = m;
             uint32_t mlt = 1;
@@ -573,9 +812,10 @@ __global__ __launch_bounds__(kWG) void k_ci_batch(const uint8_t *data, int64_t l
                 mlt *= t.card[k];
             }
         }
-        __syncthreads();
-        const TestOut o = run_test(t, lds, tile, alpha, tables ? tables + table_off[ti] : nullptr);
-        if (threadIdx.x == 0) {
+        gw.sync();
+        const TestOut o =
+            run_test(gw, t, region, W, tile, alpha, tables ? tables + table_off[ti] : nullptr);
+        if (lane == 0) {
             CiOutDev r;
             r.g2 = o.g2;
             r.p = o.p;
@@ -584,7 +824,7 @@ __global__ __launch_bounds__(kWG) void k_ci_batch(const uint8_t *data, int64_t l
             r.pad = 0;
             out[ti] = r;
         }
-        __syncthreads();
+        gw.sync();
     }
 }
 
@@ -632,11 +872,18 @@ __global__ __launch_bounds__(kWG) void k_plain_count(const uint8_t *data, int64_
     const int64_t s0 = (int64_t)blockIdx.x * spb;
     const int64_t s1 = min(m, s0 + spb);
     uint32_t *out = partials + (int64_t)blockIdx.x * T;
-    for (int64_t cb = 0; cb < T; cb += lds_words) {
-        const uint32_t Tc = (uint32_t)min((int64_t)lds_words, T - cb);
-        for (uint32_t i = threadIdx.x; i < Tc; i += kWG) lds[i] = 0u;
+    // cell ranges of at most cap cells, followed by one spill word per lane
+    const int64_t cap = (int64_t)lds_words - kWG;
+    for (int64_t cb = 0; cb < T; cb += cap) {
+        const uint32_t Tc = (uint32_t)min(cap, T - cb);
+        for (uint32_t i = threadIdx.x; i < Tc + kWG; i += kWG) lds[i] = 0u;
         __syncthreads();
-        if (s0 < s1) count_samples(t, lds, (uint32_t)cb, Tc, 0, s0, s1);
+        if (s0 < s1) {
+            if (T <= cap)
+                count_range<false>(t, lds, 0, Tc, 0, 0, s0, s1, threadIdx.x, kWG);
+            else
+                count_range<true>(t, lds, (uint32_t)cb, Tc, Tc, 0, s0, s1, threadIdx.x, kWG);
+        }
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < Tc; i += kWG) out[cb + i] = lds[i];
         __syncthreads();
@@ -658,15 +905,17 @@ __global__ __launch_bounds__(kWG) void k_plain_finish(const uint8_t *cards, cons
     }
     __syncthreads();
     uint32_t *rows = ws + T, *cols = rows + rx * Z, *strata = cols + ry * Z;
-    marginals(ws, rows, cols, strata, rx, ry, Z);
-    const double part = g2_partial<double>(ws, rows, cols, strata, rx, ry, Z);
-    const double g2 = 2.0 * wg_sum(part, t);
+    const Grp gb = Grp::workgroup();
+    marginals(gb, ws, rows, cols, strata, rx, ry, Z);
+    const double part = g2_partial<double>(gb, ws, rows, cols, strata, rx, ry, Z);
+    const double g2 = 2.0 * gb.sum(part, t);
+    const int64_t df = (int64_t)(rx - 1) * (int64_t)(ry - 1) * (int64_t)Z;
+    const double p = group_tail(gb, df, g2, t).p;
     if (threadIdx.x == 0) {
-        const int64_t df = (int64_t)(rx - 1) * (int64_t)(ry - 1) * (int64_t)Z;
         CiOutDev r;
         r.g2 = g2;
         r.df = df;
-        r.p = chi2_upper(df, g2);
+        r.p = p;
         r.flags = (r.p > alpha) ? 1 : 0;
         r.pad = 0;
         *out = r;
