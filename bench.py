@@ -59,6 +59,8 @@ def main():
     ap.add_argument("--wg-per-cu", type=int, default=0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run one device copy of this many MiB first (profiler byte calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build has no "
@@ -72,6 +74,18 @@ def main():
     from bnsynth.generate import CONFIGS
 
     torch.cuda.set_device(0)
+    if a.calib_copy_mb > 0:
+        # Profiler byte calibration: one device copy of a known size whose
+        # source has been pushed out of L2 and the Infinity Cache first (by
+        # writing a 1 GiB buffer after it), so the copy reads it from HBM.
+        n = a.calib_copy_mb << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        flush = torch.zeros(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst, flush
     dss = make_config(a.config)
     # Inputs resident in device memory before the timed region.
     handles = [bns.bns_dataset_create(d.data, d.cards) for d in dss]
