@@ -57,6 +57,10 @@ def main():
     ap.add_argument("--precision", type=int, default=0, help="0 FP32+FP64 recheck, 1 FP64")
     ap.add_argument("--lds-bytes", type=int, default=0)
     ap.add_argument("--wg-per-cu", type=int, default=0)
+    ap.add_argument("--split-min", type=int, default=0,
+                    help="smallest sample chunk of split tests (0 default, -1 never split)")
+    ap.add_argument("--units-per-group", type=int, default=0)
+    ap.add_argument("--test-group", type=int, default=0, help="0 auto, 1 wave, 2 workgroup")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -91,8 +95,10 @@ def main():
     handles = [bns.bns_dataset_create(d.data, d.cards) for d in dss]
     alphas = [d.alpha for d in dss]
     maxd = [d.max_depth for d in dss]
-    opt = bns.bns_options_default(precision=a.precision, lds_bytes=a.lds_bytes,
-                                  wg_per_cu=a.wg_per_cu)
+    knobs = dict(precision=a.precision, lds_bytes=a.lds_bytes, wg_per_cu=a.wg_per_cu,
+                 split_min_samples=a.split_min, units_per_group=a.units_per_group,
+                 test_group=a.test_group)
+    opt = bns.bns_options_default(**knobs)
 
     def step(o):
         if len(handles) == 1:
@@ -113,8 +119,7 @@ def main():
 
     # Counters of one more (untimed) step, with events around each depth's
     # persistent test launch for the roofline of that kernel.
-    topt = bns.bns_options_default(precision=a.precision, lds_bytes=a.lds_bytes,
-                                   wg_per_cu=a.wg_per_cu, timing=1)
+    topt = bns.bns_options_default(timing=1, **knobs)
     hs = step(topt)
     sks = [bns.collect(h) for h in hs]
     stats = sks[0].stats          # a multi-dataset search shares one set of counters

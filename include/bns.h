@@ -87,7 +87,17 @@ typedef struct bns_options {
                               hipGraph; default 1 */
     int32_t timing;        /* record HIP events around each depth's test launch; the
                               durations appear in bns_depth_stats.kernel_seconds */
-    int32_t reserved[8];   /* must be zero */
+    int32_t split_min_samples; /* batched form: a depth with too few tests to occupy the
+                              device cuts each test's samples into chunks of at least this
+                              many samples, counted by different groups of lanes and merged
+                              exactly (integer counts) before G^2; 0 = default (4096),
+                              -1 = never split */
+    int32_t units_per_group;   /* batched form: a depth is split only when it has at least
+                              two chunks per test for every units_per_group groups of
+                              lanes; 0 = default (1) */
+    int32_t test_group;    /* batched form: lanes that run one test: 0 = automatic,
+                              1 = one wave (64 lanes), 2 = one workgroup (256 lanes) */
+    int32_t reserved[5];   /* must be zero */
     void *stream;          /* hipStream_t; NULL = default stream */
 } bns_options;
 

@@ -44,7 +44,9 @@ class bns_options(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("recheck_band", ctypes.c_double), ("lds_bytes", ctypes.c_int32),
                 ("wg_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8),
+                ("timing", ctypes.c_int32), ("split_min_samples", ctypes.c_int32),
+                ("units_per_group", ctypes.c_int32), ("test_group", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5),
                 ("stream", ctypes.c_void_p)]
 
 

@@ -73,8 +73,11 @@ struct Ctl {
     unsigned int apply_done;           // blocks of the removal kernel that finished
     int32_t maxdeg;                    // largest frozen adjacency set at this depth
     int32_t mode;                      // test kernel: 0 one test per wave, 1 per workgroup
-    int32_t batch;                     // tickets taken per grab
-    int32_t pad2;
+    int32_t batch;                     // work units taken per grab
+    int32_t chunks;                    // sample chunks per test (1: tests are not split)
+    unsigned long long total_units;    // total_tickets * chunks
+    long long chunk_len;               // samples per chunk (a multiple of 1024)
+    unsigned long long split_cap;      // cells of each ticket's merge table
     unsigned long long level_base[kMaxLevels + 1];
     unsigned long long level_cnt[kMaxLevels + 1];
     unsigned int hist[kMaxLevels + 2];

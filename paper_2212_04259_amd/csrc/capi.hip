@@ -54,6 +54,9 @@ extern "C" void bns_options_default(bns_options *o) {
     o->wg_per_cu = 0;
     o->use_graph = 1;
     o->timing = 0;
+    o->split_min_samples = 0;
+    o->units_per_group = 0;
+    o->test_group = 0;
     o->stream = nullptr;
 }
 
@@ -71,7 +74,13 @@ static bns_status read_options(const bns_options *in, bns_options *out) {
         return fail(BNS_E_INVALID_ARG, "options.lds_bytes must be in [0, 163840]");
     if (out->wg_per_cu < 0 || out->wg_per_cu > 64)
         return fail(BNS_E_INVALID_ARG, "options.wg_per_cu must be in [0, 64]");
-    for (int i = 0; i < 8; ++i)
+    if (out->split_min_samples < -1)
+        return fail(BNS_E_INVALID_ARG, "options.split_min_samples must be -1, 0 or positive");
+    if (out->units_per_group < 0 || out->units_per_group > 1024)
+        return fail(BNS_E_INVALID_ARG, "options.units_per_group must be in [0, 1024]");
+    if (out->test_group < 0 || out->test_group > 2)
+        return fail(BNS_E_INVALID_ARG, "options.test_group must be 0, 1 or 2");
+    for (int i = 0; i < 5; ++i)
         if (out->reserved[i] != 0) return fail(BNS_E_INVALID_ARG, "options.reserved must be zero");
     return BNS_OK;
 }
@@ -124,6 +133,9 @@ struct DevCtx {
     std::mutex mu;
     // skeleton search
     DevBuf setup, adj, nbr, deg, rowcnt, rowbase, edges_tmp, edges, min_accept, rdepth, pool, ctl;
+    // merge tables and chunk counters of split depths: all zero between tests
+    DevBuf split_tab, split_cnt;
+    bool split_dirty = false;
     // CI batch and plain form
     DevBuf ci_tests, ci_z, ci_out, ci_tab, ci_taboff, plain_part, plain_ws, plain_out;
     CiOutDev *h_out = nullptr;  // pinned readback slot
@@ -141,6 +153,8 @@ struct DevCtx {
         return e;
     }
     std::vector<std::unique_ptr<GraphEntry>> graphs;  // captured depth launches
+    int search_lds = 0;  // default dynamic LDS of the skeleton test kernel (bytes)
+    int lds_per_cu = 0;
 };
 
 static std::mutex g_ctx_mu;
@@ -158,6 +172,8 @@ static bns_status get_ctx(int device, DevCtx **out) {
     HIP_TRY(hipSetDevice(device));
     HIP_TRY(hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device));
     HIP_TRY(hipDeviceGetAttribute(&c->max_lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                  device));
+    HIP_TRY(hipDeviceGetAttribute(&c->lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
                                   device));
     HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     HIP_TRY(hipHostMalloc((void **)&c->h_out, sizeof(CiOutDev), hipHostMallocDefault));
@@ -298,8 +314,8 @@ extern "C" void bns_dataset_free(bns_dataset *ds) { delete ds; }
 // ---------------------------------------------------------------------------
 static const int kDefaultLdsBytes = 40 << 10;
 
-static bns_status make_tile(const DevCtx &dc, const bns_options &o, Tile *t) {
-    int lds = o.lds_bytes ? o.lds_bytes : kDefaultLdsBytes;
+static bns_status make_tile(const DevCtx &dc, const bns_options &o, Tile *t, bool search = false) {
+    int lds = o.lds_bytes ? o.lds_bytes : (search && dc.search_lds ? dc.search_lds : kDefaultLdsBytes);
     const int static_reserve = 4096;  // TestSh + TicketSh + reductions
     if (lds + static_reserve > dc.max_lds_block) lds = dc.max_lds_block - static_reserve;
     lds &= ~255;
@@ -512,6 +528,12 @@ static bns_status dev_error(int32_t e) {
 }
 
 static const int kDepthsPerLaunch = 4;
+// Split depths: merge tables (words) shared by a depth's tickets, the largest
+// ticket count that is split, and default chunk / occupancy targets.
+static const int64_t kSplitWords = 8 << 20;
+static const int64_t kSplitTickets = 32768;
+static const int32_t kSplitMinDefault = 4096;
+static const int32_t kUnitsPerGroupDefault = 1;
 
 // Captures (once per distinct argument set) K consecutive depth sequences as
 // one executable graph; the depth index lives in the device control block, so
@@ -548,14 +570,15 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
                               const double *alpha, const int32_t *maxd, const bns_options &o,
                               std::vector<bns_skeleton *> &outs) {
     Tile tile;
-    bns_status st = make_tile(dc, o, &tile);
+    if (!dc.search_lds) dc.search_lds = depth_tests_fit_lds(dc.lds_per_cu);
+    bns_status st = make_tile(dc, o, &tile, true);
     if (st != BNS_OK) return st;
     hipStream_t s = o.stream ? (hipStream_t)o.stream : dc.stream;
 
     std::vector<ProbDev> probs((size_t)P);
     std::vector<int32_t> var2prob;
     std::vector<uint8_t> gcards;
-    int64_t adj_total = 0, pairs_total = 0;
+    int64_t adj_total = 0, pairs_total = 0, m_max = 1;
     int32_t G = 0, nmax = 0, dmax = -1;
     bool unbounded = false;
     for (int32_t k = 0; k < P; ++k) {
@@ -567,6 +590,7 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
         adj_total += (int64_t)d->n * d->n;
         pairs_total += (int64_t)d->n * (d->n - 1) / 2;
         nmax = std::max(nmax, d->n);
+        m_max = std::max(m_max, d->m);
         if (maxd[k] < 0) unbounded = true;
         dmax = std::max(dmax, maxd[k]);
     }
@@ -603,6 +627,13 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     HIP_TRY(dc.min_accept.ensure(sizeof(unsigned long long) * (size_t)pairs_total));
     HIP_TRY(dc.ctl.ensure(sizeof(Ctl)));
     HIP_TRY(dc.pool.ensure(sizeof(int32_t) * 1024));
+    if (!dc.split_tab.p || dc.split_dirty) {
+        HIP_TRY(dc.split_tab.ensure(sizeof(uint32_t) * (size_t)kSplitWords));
+        HIP_TRY(dc.split_cnt.ensure(sizeof(uint32_t) * (size_t)kSplitTickets));
+        HIP_TRY(hipMemsetAsync(dc.split_tab.p, 0, dc.split_tab.bytes, s));
+        HIP_TRY(hipMemsetAsync(dc.split_cnt.p, 0, dc.split_cnt.bytes, s));
+        dc.split_dirty = false;
+    }
 
     DepthArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -626,6 +657,14 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     a.pool = dc.pool.as<int32_t>();
     a.ctl = dc.ctl.as<Ctl>();
     a.tile = tile;
+    a.split_tab = dc.split_tab.as<uint32_t>();
+    a.split_cnt = dc.split_cnt.as<uint32_t>();
+    a.split_words = kSplitWords;
+    a.split_tickets = kSplitTickets;
+    a.m_max = m_max;
+    a.split_min = o.split_min_samples == 0 ? kSplitMinDefault : o.split_min_samples;
+    a.units_per_group = o.units_per_group == 0 ? kUnitsPerGroupDefault : o.units_per_group;
+    a.mode_policy = o.test_group;
 
     const int lds_bytes = tile.lds_words * 4;
     int wg = o.wg_per_cu ? o.wg_per_cu : depth_tests_max_wg_per_cu(lds_bytes);
@@ -695,7 +734,10 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
         HIP_TRY(hipMemcpyAsync(dc.h_ctl, dc.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         const Ctl &c = *dc.h_ctl;
-        if (c.error) return dev_error(c.error);
+        if (c.error) {
+            dc.split_dirty = true;  // a depth may have stopped with partial merge tables
+            return dev_error(c.error);
+        }
         const int reached = c.depth;  // depths d .. reached-1 completed
         for (int dd = d; dd < reached; ++dd) {
             const DepthStatDev &sd = c.stats[dd];

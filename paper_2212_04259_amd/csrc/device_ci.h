@@ -48,6 +48,22 @@ struct TestOut {
 // Groups.  Reductions use a fixed order and broadcast lane 0's result, so
 // every lane sees the same, run-to-run deterministic value.
 // ---------------------------------------------------------------------------
+// Values uniform across a wave (read from LDS by every lane) moved to scalar
+// registers, which keeps the per-test state out of the vector register file.
+BNS_INLINE uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+BNS_INLINE int32_t uni(int32_t v) { return (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)v); }
+BNS_INLINE uint64_t uni(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+BNS_INLINE int64_t uni(int64_t v) { return (int64_t)uni((uint64_t)v); }
+BNS_INLINE unsigned long long uni(unsigned long long v) { return (unsigned long long)uni((uint64_t)v); }
+BNS_INLINE long long uni(long long v) { return (long long)uni((uint64_t)v); }
+BNS_INLINE double uni(double v) { return __builtin_bit_cast(double, uni(__builtin_bit_cast(uint64_t, v))); }
+template <typename T>
+BNS_INLINE T *uni(T *p) { return (T *)uni((uint64_t)p); }
+
 template <typename T>
 BNS_INLINE T wave_sum(T v) {
 #pragma unroll
@@ -84,6 +100,15 @@ struct Grp {
         for (int w = 0; w < kWaves; ++w) s += t.red_d[w];
         __syncthreads();
         return s;
+    }
+    // Lane 0's value to every lane of the group.
+    BNS_INLINE uint32_t bcast(uint32_t v, TestSh &t) const {
+        if (!block) return __shfl(v, 0, 64);
+        if (threadIdx.x == 0) t.bcast_i[0] = (int32_t)v;
+        __syncthreads();
+        v = (uint32_t)t.bcast_i[0];
+        __syncthreads();
+        return v;
     }
     BNS_INLINE float sum(float v, TestSh &t) const {
         v = wave_sum(v);
@@ -305,6 +330,7 @@ BNS_INLINE void count16(const u32x4 (&v)[NC], const uint32_t (&mul)[NC], uint32_
     }
 }
 
+// Groups of 16 samples [q0, q1), lane `rank` of S taking every S-th group.
 template <int NC, bool kChunk>
 BNS_INLINE void count_fixed(const TestSh &t, uint32_t *tab, uint32_t cbase, uint32_t Tc,
                             uint32_t trash, int logR, int64_t q0, int64_t q1, int rank, int S) {
@@ -316,27 +342,27 @@ BNS_INLINE void count_fixed(const TestSh &t, uint32_t *tab, uint32_t cbase, uint
     uint32_t mul[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-        cp[k] = uniform_col(t.col[k]);
+        cp[k] = uniform_col(t.col[k]) + q0;
         mul[k] = __builtin_amdgcn_readfirstlane(t.mult[k]);
     }
     // sample groups are < 2^27, so 32-bit group indices suffice
-    uint32_t q = (uint32_t)q0 + (uint32_t)rank;
-    const uint32_t qe = (uint32_t)q1;
+    const uint32_t n = (uint32_t)(q1 - q0);
     const uint32_t us = (uint32_t)S;
-    for (; q + (U - 1) * us < qe; q += U * us) {
+    uint32_t i = (uint32_t)rank;
+    for (; i + (U - 1) * us < n; i += U * us) {
         u32x4 v[U][NC];
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int k = 0; k < NC; ++k) v[u][k] = cp[k][q + u * us];
+            for (int k = 0; k < NC; ++k) v[u][k] = cp[k][i + u * us];
 #pragma unroll
         for (int u = 0; u < U; ++u)
             count16<NC, kChunk>(v[u], mul, tab, cbase, Tc, trash, logR, rep, spill);
     }
-    for (; q < qe; q += us) {
+    for (; i < n; i += us) {
         u32x4 v[NC];
 #pragma unroll
-        for (int k = 0; k < NC; ++k) v[k] = cp[k][q];
+        for (int k = 0; k < NC; ++k) v[k] = cp[k][i];
         count16<NC, kChunk>(v, mul, tab, cbase, Tc, trash, logR, rep, spill);
     }
 }
@@ -493,16 +519,18 @@ struct Plan {
     int32_t err;
 };
 
-// W: LDS words available to the group; S: lanes in the group.
-BNS_INLINE Plan make_plan(const TestSh &t, uint32_t W, int max_rep_log2, int S) {
+// W: LDS words available to the group; S: lanes in the group; msamp: samples
+// the group counts (replication must stay cheap against them).
+BNS_INLINE Plan make_plan(const TestSh &t, uint32_t W, int max_rep_log2, int S, int64_t msamp) {
     Plan P;
     P.err = kDevOk;
-    P.rx = t.card[0];
-    P.ry = t.card[1];
+    P.rx = uni(t.card[0]);
+    P.ry = uni(t.card[1]);
     P.rxy = P.rx * P.ry;
     uint64_t ns = 1;
-    for (int k = 2; k < t.ncols; ++k) {
-        ns *= t.card[k];
+    const int nc = uni(t.ncols);
+    for (int k = 2; k < nc; ++k) {
+        ns *= uni(t.card[k]);
         if (ns * P.rxy > kMaxCells) {
             P.err = kDevTableTooLarge;
             ns = 1;
@@ -520,7 +548,7 @@ BNS_INLINE Plan make_plan(const TestSh &t, uint32_t W, int max_rep_log2, int S) 
         P.nchunks = 1;
         // Replicate while the replicated table fits next to the reduced one
         // and the zero/reduce work stays small against the increments.
-        const int64_t m = t.m;
+        const int64_t m = msamp;
         while (P.logR < max_rep_log2) {
             const uint64_t R2 = 2ull << P.logR;
             if ((uint64_t)P.T * R2 + P.T + marg > W) break;
@@ -541,11 +569,27 @@ BNS_INLINE Plan make_plan(const TestSh &t, uint32_t W, int max_rep_log2, int S) 
     return P;
 }
 
+// Reads a counter that other workgroups updated with device-scope atomics.
+BNS_INLINE uint32_t load_device(const uint32_t *p) {
+    return __hip_atomic_load(const_cast<uint32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Where the counts of a pass come from and where they go.
+struct Src {
+    const uint32_t *gsrc;  // non-null: read the table from here (merged chunks of a split test)
+    uint32_t *gdst;        // non-null: add the counted table to here, no G^2
+    int64_t s0, s1;        // samples counted (s0 a multiple of 16)
+};
+
 // Counts, marginals and the G^2 sum of one test over all its passes (G^2 in
 // FP64 when fp64, else FP32).  Leaves the last pass's table and marginals in
 // LDS (returned through *tab_out).  gtab (may be null) receives the counts.
+// With src.gsrc the table is read instead of counted (the plan must have no
+// replication); with src.gdst the counts of samples [s0, s1) are added to
+// src.gdst with device-scope atomics (non-zero cells only) and nothing else
+// is computed.
 BNS_INLINE double table_pass(const Grp &g, TestSh &t, const Plan &P, uint32_t *lds, uint32_t *gtab,
-                             bool fp64, const uint32_t **tab_out) {
+                             const Src &src, bool fp64, const uint32_t **tab_out) {
     double part64 = 0.0;
     float part32 = 0.0f;
     const uint32_t *tab = lds;
@@ -563,16 +607,31 @@ BNS_INLINE double table_pass(const Grp &g, TestSh &t, const Plan &P, uint32_t *l
         uint32_t *rows = lds + head + (logR > 0 ? Tc : 0u);
         uint32_t *cols = rows + P.rx * Zc;
         uint32_t *strata = cols + P.ry * Zc;
-        for (uint32_t i = g.rank; i < head; i += g.size) rep_tab[i] = 0u;
-        g.sync();
-        if (chunked)
-            count_range<true>(t, rep_tab, P.rxy * z0, Tc, Tc, 0, 0, t.m, g.rank, g.size);
-        else
-            count_range<false>(t, rep_tab, 0, Tc, 0, logR, 0, t.m, g.rank, g.size);
-        g.sync();
-        if (logR > 0) {
-            reduce_replicas(rep_tab, red, Tc, logR, g.rank, g.size);
+        if (src.gsrc) {
+            const uint32_t *gs = src.gsrc + P.rxy * z0;
+            for (uint32_t i = g.rank; i < Tc; i += g.size) red[i] = load_device(gs + i);
             g.sync();
+        } else {
+            for (uint32_t i = g.rank; i < head; i += g.size) rep_tab[i] = 0u;
+            g.sync();
+            if (chunked)
+                count_range<true>(t, rep_tab, P.rxy * z0, Tc, Tc, 0, src.s0, src.s1, g.rank, g.size);
+            else
+                count_range<false>(t, rep_tab, 0, Tc, 0, logR, src.s0, src.s1, g.rank, g.size);
+            g.sync();
+            if (logR > 0) {
+                reduce_replicas(rep_tab, red, Tc, logR, g.rank, g.size);
+                g.sync();
+            }
+        }
+        if (src.gdst) {
+            uint32_t *dst = src.gdst + P.rxy * z0;
+            for (uint32_t i = g.rank; i < Tc; i += g.size) {
+                const uint32_t v = red[i];
+                if (v) __hip_atomic_fetch_add(dst + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (c + 1 < P.nchunks) g.sync();
+            continue;
         }
         if (gtab)
             for (uint32_t i = g.rank; i < Tc; i += g.size) gtab[P.rxy * z0 + i] = red[i];
@@ -583,6 +642,7 @@ BNS_INLINE double table_pass(const Grp &g, TestSh &t, const Plan &P, uint32_t *l
         if (c + 1 < P.nchunks) g.sync();
     }
     *tab_out = tab;
+    if (src.gdst) return 0.0;
     if (fp64) return 2.0 * g.sum(part64, t);
     return 2.0 * (double)g.sum(part32, t);
 }
@@ -627,12 +687,14 @@ BNS_INLINE Tail group_tail(const Grp &g, int64_t df, double g2, TestSh &t) {
 
 // Runs one complete test with the description in t (all lanes of the group,
 // uniform control flow) in W words of LDS at lds.  alpha drives the decision;
-// gtab (may be null) receives the exact table.
+// gtab (may be null) receives the exact table.  src: the samples counted, or
+// the merged table of a split test to evaluate, or a merge target (then only
+// the chunk [s0, s1) is counted and added there; no G^2, no decision).
 BNS_INLINE TestOut run_test(const Grp &g, TestSh &t, uint32_t *lds, uint32_t W, const Tile &tile,
-                            double alpha, uint32_t *gtab) {
+                            double alpha, uint32_t *gtab, const Src &src) {
     TestOut o;
     o.flags = 0;
-    const Plan P = make_plan(t, W, tile.max_rep_log2, g.size);
+    const Plan P = make_plan(t, W, src.gsrc ? 0 : tile.max_rep_log2, g.size, src.s1 - src.s0);
     o.err = P.err;
     o.df = P.df;
     if (P.err != kDevOk) {
@@ -647,7 +709,12 @@ BNS_INLINE TestOut run_test(const Grp &g, TestSh &t, uint32_t *lds, uint32_t W, 
     bool fp64 = tile.fp64 != 0;
     double g2 = 0.0, p = 1.0;
     for (int round = 0; round < 2; ++round) {
-        g2 = table_pass(g, t, P, lds, round == 0 ? gtab : nullptr, fp64, &tab);
+        g2 = table_pass(g, t, P, lds, round == 0 ? gtab : nullptr, src, fp64, &tab);
+        if (src.gdst) {  // merge only: no statistic, no decision
+            o.g2 = 0.0;
+            o.p = 1.0;
+            return o;
+        }
         Tail tl = group_tail(g, P.df, g2, t);
         p = tl.p;
         if (fp64 || P.df <= 0) break;

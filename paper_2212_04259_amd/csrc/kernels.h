@@ -33,6 +33,19 @@ struct DepthArgs {
     int64_t n_pairs;          // variable pairs over all problems
     int32_t test_waves;       // waves of the persistent test grid
     int32_t edge_grid;        // workgroups of the per-edge kernels (scatter, removal)
+    // Sample splitting of depths with few tests: a test's samples are cut
+    // into chunks counted by different groups and merged into a per-ticket
+    // table in split_tab (all zero between tests); split_cnt[ticket] counts
+    // the chunks merged so far (zero between tests).
+    uint32_t *split_tab;
+    uint32_t *split_cnt;
+    int64_t split_words;      // words of split_tab
+    int64_t split_tickets;    // entries of split_cnt: depths with more tickets are not split
+    int64_t m_max;            // largest sample count over problems
+    int32_t split_min;        // smallest chunk in samples; <= 0 disables splitting
+    int32_t units_per_group;  // work units aimed for per concurrent group when splitting
+    int32_t mode_policy;      // 0 automatic, 1 one test per wave, 2 one test per workgroup
+    int32_t pad2;
 };
 
 hipError_t launch_depth_prepare(const DepthArgs &a, hipStream_t s);   // snapshot .. scatter
@@ -40,6 +53,7 @@ hipError_t launch_depth_tests(const DepthArgs &a, int grid, hipStream_t s);
 hipError_t launch_depth_apply(const DepthArgs &a, hipStream_t s);     // removals + finalize
 hipError_t launch_init_search(const DepthArgs &a, hipStream_t s);     // complete graph, reset
 int depth_tests_max_wg_per_cu(int lds_bytes);
+int depth_tests_fit_lds(int lds_per_cu);  // default dynamic LDS at full occupancy
 hipError_t allow_dynamic_lds(int bytes);  // raises the per-kernel dynamic LDS limit
 
 // Batched CI tests without PC control.

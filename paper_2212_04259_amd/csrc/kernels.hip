@@ -238,6 +238,9 @@ __global__ __launch_bounds__(kWG) void k_edges(DepthArgs A) {
 // One wave: ticket levels.  Edges are ordered by their number of levels,
 // descending, so the edges with a test of rank r form a prefix; level L holds
 // ranks [2^L - 1, 2^(L+1) - 1) of the first level_cnt[L] edges, rank-major.
+// Tickets per test wave from which one test per wave beats one per workgroup.
+constexpr unsigned long long kWaveModeRounds = 6;
+
 BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist) {
     const int lane = threadIdx.x & 63;
     // cursor[lv] = number of edges with more than lv levels (bucket start in
@@ -281,19 +284,47 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
         if (any_bad) c->error = kDevTooManyTests;
         c->total_tickets = any_bad ? 0ull : total;
         c->ticket_ctr = 0;
-        // Few tickets: a workgroup per test (shorter tests, less speculation);
-        // otherwise a wave per test.  Grabs of several tickets amortise the
-        // decode latency when there is work for several rounds.
+        // Group per test: a wave (no workgroup barriers), or a workgroup
+        // (4x the LDS and lanes per test: shorter tests, less speculation).
+        // Automatic: a workgroup per test unless there are tickets for
+        // several rounds of all waves.
         const unsigned long long tw = (unsigned long long)max(A.test_waves, 1);
-        if (total < 8ull * tw) {
-            c->mode = 1;
-            const unsigned long long per = total / (4ull * (tw / kWaves + 1));
-            c->batch = (int)max(1ull, min(per, (unsigned long long)kSlotsPerWave));
-        } else {
-            c->mode = 0;
-            const unsigned long long per = total / (4ull * tw);
-            c->batch = (int)max(1ull, min(per, (unsigned long long)kSlotsPerWave));
+        const int mode = (A.mode_policy == 2) ? 1
+                       : (A.mode_policy == 1) ? 0
+                       : (total < kWaveModeRounds * tw ? 1 : 0);
+        const unsigned long long groups = mode ? max(tw / kWaves, 1ull) : tw;
+        // Fewer tickets than half the groups: cut each test's samples into
+        // chunks of at least split_min samples, counted by different groups
+        // and merged in device memory (about units_per_group units per group).
+        // With more tickets the merges cost more than the idle groups.
+        unsigned long long C = 1, cap = 0;
+        long long Lc = A.m_max;
+        if (A.split_min > 0 && total > 0 && total <= (unsigned long long)A.split_tickets) {
+            const unsigned long long want =
+                (unsigned long long)max(A.units_per_group, 1) * groups / total;
+            const unsigned long long by_len = (unsigned long long)(A.m_max / A.split_min);
+            const unsigned long long cc = min(min(want, by_len), 65536ull);
+            cap = (unsigned long long)A.split_words / total;
+            if (cc >= 2 && cap >= 64) {
+                const long long per = (A.m_max + (long long)cc - 1) / (long long)cc;
+                Lc = (per + 1023) & ~1023ll;
+                C = (unsigned long long)((A.m_max + Lc - 1) / Lc);
+            }
         }
+        if (C < 2) {
+            C = 1;
+            Lc = A.m_max;
+            cap = 0;
+        }
+        c->mode = mode;
+        c->chunks = (int)C;
+        c->chunk_len = Lc;
+        c->split_cap = cap;
+        c->total_units = any_bad ? 0ull : total * C;
+        // Grabs of several units amortise the decode latency when there is
+        // work for several rounds.
+        const unsigned long long per = total * C / (4ull * groups);
+        c->batch = (int)max(1ull, min(per, (unsigned long long)kSlotsPerWave));
         if (total == 0 || any_bad) {
             c->done = 1;
         } else if (d < kMaxDepths) {
@@ -434,9 +465,12 @@ struct Desc {
     double alpha;
     unsigned long long r;
     int64_t e;
+    unsigned long long tk;  // ticket
+    int32_t chunk;          // sample chunk of the ticket (split depths)
+    int32_t pad;
     int32_t valid;
     int32_t ncols;
-    int32_t var[kMaxCols];
+    uint16_t var[kMaxCols];  // variable ids (n <= 65535)
     uint8_t card[kMaxCols];
 };
 
@@ -453,14 +487,14 @@ BNS_INLINE uint64_t bnm(const uint64_t *tab, int stride, int rows, int64_t n, in
 // subsets with the current prefix whose next element is below x
 // (hockey-stick identity).  Writes the positions to out[0..d).
 BNS_INLINE void unrank_lane(const uint64_t *tab, int stride, int rows, int64_t p, int d,
-                            uint64_t rr, int32_t *out) {
+                            uint64_t rr, uint16_t *out) {
     int64_t x0 = 0;
     for (int k = 0; k < d; ++k) {
         const int j = d - k - 1;
         const uint64_t base = bnm(tab, stride, rows, p - x0, j + 1);
         int64_t x = x0;
         while (x + 1 <= p - j - 1 && base - bnm(tab, stride, rows, p - (x + 1), j + 1) <= rr) ++x;
-        out[k] = (int32_t)x;
+        out[k] = (uint16_t)x;
         rr -= base - bnm(tab, stride, rows, p - x, j + 1);
         x0 = x + 1;
     }
@@ -468,7 +502,8 @@ BNS_INLINE void unrank_lane(const uint64_t *tab, int stride, int rows, int64_t p
 
 BNS_INLINE void decode_ticket(const DepthArgs &A, const unsigned long long *lvl_base,
                               const unsigned long long *lvl_cnt, int nlev, unsigned long long tk,
-                              int d, const uint64_t *btab, int bstride, int brows, Desc &q) {
+                              int d, const uint64_t *btab, int bstride, int brows, bool skip_ok,
+                              Desc &q) {
     int lo = 0, hi = nlev - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -484,7 +519,7 @@ BNS_INLINE void decode_ticket(const DepthArgs &A, const unsigned long long *lvl_
     const EdgeRec rec = A.edges[e];
     const unsigned long long ma =
         __hip_atomic_load(&A.min_accept[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    q.valid = (r < rec.n && r <= ma) ? 1 : 0;
+    q.valid = (r < rec.n && (!skip_ok || r <= ma)) ? 1 : 0;
     if (!q.valid) return;
     const ProbDev P = A.probs[rec.prob];
     q.data = P.data;
@@ -494,33 +529,39 @@ BNS_INLINE void decode_ticket(const DepthArgs &A, const unsigned long long *lvl_
     q.r = r;
     q.e = e;
     q.ncols = d + 2;
-    q.var[0] = rec.i;
-    q.var[1] = rec.j;
+    q.var[0] = (uint16_t)rec.i;
+    q.var[1] = (uint16_t)rec.j;
     if (d > 0) {
         const bool sideA = r < rec.nA;
         const int owner = sideA ? rec.i : rec.j;
         const int skip = sideA ? rec.posj : rec.posi;
         const int64_t p = sideA ? rec.pA : rec.pB;
         unrank_lane(btab, bstride, brows, p, d, sideA ? r : r - rec.nA, q.var + 2);
+        // positions -> variable ids, up to 8 loads in flight at a time
         const int32_t *nbo = A.nbr + P.adj_off + (int64_t)owner * P.n;
-        int32_t vv[kMaxZ];
+        for (int k0 = 0; k0 < d; k0 += 8) {
+            uint16_t vv[8];
 #pragma unroll
-        for (int k = 0; k < kMaxZ; ++k)
-            if (k < d) {
-                const int pos = q.var[2 + k];
-                vv[k] = nbo[pos + (pos >= skip ? 1 : 0)];
-            }
+            for (int k = 0; k < 8; ++k)
+                if (k0 + k < d) {
+                    const int pos = q.var[2 + k0 + k];
+                    vv[k] = (uint16_t)nbo[pos + (pos >= skip ? 1 : 0)];
+                }
 #pragma unroll
-        for (int k = 0; k < kMaxZ; ++k)
-            if (k < d) q.var[2 + k] = vv[k];
+            for (int k = 0; k < 8; ++k)
+                if (k0 + k < d) q.var[2 + k0 + k] = vv[k];
+        }
     }
-    uint8_t cc[kMaxCols];
+    const uint8_t *cards = A.cards + P.var_off;
+    for (int k0 = 0; k0 < d + 2; k0 += 8) {
+        uint8_t cc[8];
 #pragma unroll
-    for (int k = 0; k < kMaxCols; ++k)
-        if (k < d + 2) cc[k] = A.cards[P.var_off + q.var[k]];
+        for (int k = 0; k < 8; ++k)
+            if (k0 + k < d + 2) cc[k] = cards[q.var[k0 + k]];
 #pragma unroll
-    for (int k = 0; k < kMaxCols; ++k)
-        if (k < d + 2) q.card[k] = cc[k];
+        for (int k = 0; k < 8; ++k)
+            if (k0 + k < d + 2) q.card[k0 + k] = cc[k];
+    }
 }
 
 // Stages a decoded test into the group's TestSh (all lanes of the group).
@@ -547,6 +588,13 @@ BNS_INLINE unsigned long long bcast_u64(unsigned long long v) {
     return ((unsigned long long)hi << 32) | lo;
 }
 
+// Cells of the test staged in t (saturates above 2^32).
+BNS_INLINE uint64_t table_cells(const TestSh &t) {
+    uint64_t T = 1;
+    for (int k = 0; k < t.ncols && T <= 0xffffffffull; ++k) T *= t.card[k];
+    return T;
+}
+
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k_depth_tests(DepthArgs A) {
     extern __shared__ uint32_t lds[];
     __shared__ TestSh tsh[kWaves];
@@ -555,10 +603,22 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
     __shared__ unsigned long long lvl_cnt[kMaxLevels + 1];
     __shared__ uint64_t btab_lds[kBinomLds];
     __shared__ unsigned long long grab;
+    // per-group tallies (kept in LDS: no vector registers across tests)
+    __shared__ unsigned long long tal_exec[kWaves], tal_re[kWaves];
+    __shared__ double tal_bytes[kWaves];
     Ctl *c = A.ctl;
     if (c->done || c->error) return;
+    if (threadIdx.x < kWaves) {
+        tal_exec[threadIdx.x] = 0;
+        tal_re[threadIdx.x] = 0;
+        tal_bytes[threadIdx.x] = 0.0;
+    }
     const int d = c->depth;
     const unsigned long long total = c->total_tickets;
+    const unsigned long long units = c->total_units;
+    const int C = c->chunks;
+    const long long Lc = c->chunk_len;
+    const uint64_t cap = c->split_cap;
     const int mode = c->mode;
     const int B = c->batch;
     if (threadIdx.x <= kMaxLevels) {
@@ -582,9 +642,6 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
     int nlev = 0;
     while (nlev < kMaxLevels && lvl_cnt[nlev] > 0) ++nlev;
     const int w = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    unsigned long long executed = 0, rechecks = 0;
-    double bytes = 0.0;
     // mode 0: one test per wave in a quarter of the LDS; mode 1: one test per
     // workgroup in all of it
     const Grp g = mode ? Grp::workgroup() : Grp::wave();
@@ -592,6 +649,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
     Desc *mine = mode ? slots : slots + w * kSlotsPerWave;
     const uint32_t W = mode ? (uint32_t)A.tile.lds_words : (uint32_t)A.tile.lds_words / kWaves;
     uint32_t *region = mode ? lds : lds + (uint32_t)w * W;
+    const int ti = mode ? 0 : w;  // tally slot of the group
+    // A unit is (ticket, chunk); chunk-major order puts the chunks of one
+    // ticket far apart, so they run on different groups at the same time.
     for (;;) {
         unsigned long long base = 0;
         if (g.rank == 0) base = atomicAdd(&c->ticket_ctr, (unsigned long long)B);
@@ -603,31 +663,88 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
         } else {
             base = bcast_u64(base);
         }
-        if (base >= total) break;
-        const int cnt = (int)min((unsigned long long)B, total - base);
-        if (g.rank < cnt)
-            decode_ticket(A, lvl_base, lvl_cnt, nlev, base + g.rank, d, btab, bstride, brows,
-                          mine[g.rank]);
+        if (base >= units) break;
+        const int cnt = (int)min((unsigned long long)B, units - base);
+        if (g.rank < cnt) {
+            const unsigned long long u = base + g.rank;
+            const unsigned long long ch = (C > 1) ? u / total : 0ull;
+            const unsigned long long tk = u - ch * total;
+            Desc &q = mine[g.rank];
+            decode_ticket(A, lvl_base, lvl_cnt, nlev, tk, d, btab, bstride, brows, C == 1, q);
+            q.tk = tk;
+            q.chunk = (int32_t)ch;
+        }
         g.sync();
         for (int j = 0; j < cnt; ++j) {
             const Desc &q = mine[j];
-            if (!q.valid) continue;
+            if (!uni(q.valid)) continue;
             stage_test(g, q, t);
-            const TestOut o = run_test(g, t, region, W, A.tile, q.alpha, nullptr);
-            if (g.rank == 0) {
-                ++executed;
-                bytes += (double)q.ncols * (double)q.m;
-                if (o.flags & 2) ++rechecks;
-                if (o.err) c->error = o.err;
-                if (o.flags & 1) atomicMin(&A.min_accept[q.e], q.r);
+            const int64_t qm = uni(q.m);
+            // Split depths: unit (ticket, chunk) counts its chunk of samples
+            // into the ticket's merge table; the group that merges the last
+            // chunk evaluates the test from the merged table and clears it.
+            // A test whose table exceeds the merge table runs whole in chunk 0.
+            Src src{nullptr, nullptr, 0, qm};
+            uint32_t *gt = nullptr;
+            uint32_t nch = 1;
+            if (C > 1) {
+                const int chunk = uni(q.chunk);
+                const int64_t s0 = (int64_t)chunk * Lc;
+                nch = (uint32_t)((qm + Lc - 1) / Lc);
+                if (nch > 1 && table_cells(t) <= cap) {
+                    if (s0 >= qm) continue;
+                    gt = A.split_tab + uni(q.tk) * cap;
+                    src.gdst = gt;
+                    src.s0 = s0;
+                    src.s1 = min(qm, s0 + (int64_t)Lc);
+                } else if (chunk != 0) {
+                    continue;
+                }
+            }
+            for (;;) {
+                const TestOut o = run_test(g, t, region, W, A.tile, uni(q.alpha), nullptr, src);
+                if (g.rank == 0) tal_bytes[ti] += (double)q.ncols * (double)(src.s1 - src.s0);
+                if (src.gdst) {
+                    // Device-scope atomics are performed at the device's
+                    // coherence point; waiting for this group's table atomics
+                    // (workgroup-scope release) before the chunk is counted
+                    // orders them before the counter, and the evaluating
+                    // group reads the table with device-scope loads issued
+                    // after it has seen the final count.  An agent-scope
+                    // fence would also write back and invalidate this XCD's
+                    // L2, evicting every other test's columns.
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    g.sync();
+                    uint32_t prev = 0;
+                    if (g.rank == 0) prev = atomicAdd(&A.split_cnt[q.tk], 1u);
+                    prev = g.bcast(prev, t);
+                    if (prev + 1 != nch) break;
+                    if (g.rank == 0) A.split_cnt[q.tk] = 0u;
+                    src = Src{gt, nullptr, 0, 0};  // evaluate the merged table
+                    continue;
+                }
+                if (src.gsrc) {
+                    g.sync();
+                    const uint32_t T = (uint32_t)table_cells(t);
+                    for (uint32_t i = g.rank; i < T; i += g.size) gt[i] = 0u;
+                }
+                if (g.rank == 0) {
+                    ++tal_exec[ti];
+                    if (o.flags & 2) ++tal_re[ti];
+                    if (o.err) c->error = o.err;
+                    if (o.flags & 1) atomicMin(&A.min_accept[q.e], q.r);
+                }
+                break;
             }
             g.sync();
         }
     }
-    if (lane == 0 && d < kMaxDepths) {
-        if (executed) atomicAdd(&c->stats[d].executed, executed);
-        if (rechecks) atomicAdd(&c->stats[d].rechecks, rechecks);
-        if (executed) atomicAdd(&c->stats[d].operand_bytes, bytes);
+    __syncthreads();
+    if (threadIdx.x < kWaves && d < kMaxDepths) {
+        const int k = threadIdx.x;
+        if (tal_exec[k]) atomicAdd(&c->stats[d].executed, tal_exec[k]);
+        if (tal_re[k]) atomicAdd(&c->stats[d].rechecks, tal_re[k]);
+        if (tal_bytes[k] > 0.0) atomicAdd(&c->stats[d].operand_bytes, tal_bytes[k]);
     }
 }
 
@@ -777,6 +894,22 @@ int depth_tests_max_wg_per_cu(int lds_bytes) {
     return nb > 0 ? nb : 1;
 }
 
+int depth_tests_fit_lds(int lds_per_cu) {
+    // The workgroups per compute unit that the registers allow, then the
+    // dynamic LDS that leaves each of them a share of the compute unit's LDS
+    // rounded down to 2 KB: the LDS is allocated in granules, so a share
+    // sized to the byte can cost a workgroup per compute unit.
+    const int target = depth_tests_max_wg_per_cu(4096);
+    hipFuncAttributes fa;
+    int stat = 16384;
+    if (hipFuncGetAttributes(&fa, (const void *)k_depth_tests) == hipSuccess) stat = (int)fa.sharedSizeBytes;
+    if (lds_per_cu <= 0) lds_per_cu = 65536;
+    const int share = (lds_per_cu / max(target, 1)) & ~2047;
+    int b = (share - stat) & ~255;
+    while (b > 4096 && depth_tests_max_wg_per_cu(b) < target) b -= 256;
+    return max(b, 4096);
+}
+
 // ---------------------------------------------------------------------------
 // Batched CI tests (bns_ci_batch): one test per wave, same device path as the
 // skeleton search.
@@ -814,7 +947,8 @@ __global__ __launch_bounds__(kWG) void k_ci_batch(const uint8_t *data, int64_t l
         }
         gw.sync();
         const TestOut o =
-            run_test(gw, t, region, W, tile, alpha, tables ? tables + table_off[ti] : nullptr);
+            run_test(gw, t, region, W, tile, alpha, tables ? tables + table_off[ti] : nullptr,
+                     Src{nullptr, nullptr, 0, m});
         if (lane == 0) {
             CiOutDev r;
             r.g2 = o.g2;

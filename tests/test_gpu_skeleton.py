@@ -61,12 +61,30 @@ def test_plain_matches_golden(bns, k):
 @pytest.mark.parametrize("opts", [
     dict(lds_bytes=16384), dict(lds_bytes=32768, wg_per_cu=1), dict(lds_bytes=65536),
     dict(use_graph=0), dict(timing=1), dict(recheck_band=0.0),
+    dict(split_min_samples=-1), dict(split_min_samples=1024, units_per_group=16),
+    dict(split_min_samples=1024, units_per_group=16, lds_bytes=8192),
+    dict(test_group=2), dict(test_group=2, split_min_samples=-1),
+    dict(test_group=2, split_min_samples=1024, units_per_group=64),
+    dict(test_group=1, split_min_samples=2048, units_per_group=4, precision=1),
 ])
 def test_tile_shapes_and_modes_identical(bns, opts):
     g = load_golden(2)["datasets"][0]
     ds = _cfg(2)[0]
     got = _run(bns, ds, "cfg2", **opts)
     compare_skeleton(got, g, f"cfg2 {opts}")
+
+
+def test_split_tables_stay_clean_across_searches(bns):
+    # Merge tables of split depths are cleared by the group that evaluates
+    # each test; back-to-back searches of different shapes must not see
+    # leftovers.
+    for k, opts in ((2, dict(split_min_samples=1024, units_per_group=32)),
+                    (1, dict(split_min_samples=1024, units_per_group=32)),
+                    (3, dict(split_min_samples=1024, units_per_group=8)),
+                    (2, dict(split_min_samples=1024, units_per_group=32, test_group=2))):
+        g = load_golden(k)["datasets"][0]
+        got = _run(bns, _cfg(k)[0], f"cfg{k}", **opts)
+        compare_skeleton(got, g, f"cfg{k} {opts}")
 
 
 def test_cfg4_full_size(bns):
@@ -83,11 +101,17 @@ def test_cfg5_batch_of_64(bns):
     assert [d.sha256() for d in dss] == [g["sha256"] for g in gold]
     print(f"skeleton cfg5 batch of {len(dss)}", flush=True)
     handles = [bns.bns_dataset_create(d.data, d.cards) for d in dss]
-    outs = bns.bns_pc_skeleton_batch(handles, [d.alpha for d in dss], [d.max_depth for d in dss])
-    assert len(outs) == len(dss)
-    for i, (got, g) in enumerate(zip(outs, gold)):
-        adj_ok = compare_adj_only(got, g)
-        assert adj_ok, f"cfg5[{i}]"
+    # default options, then chunks shorter than most datasets' sample counts
+    # (ragged chunk counts per test within one depth)
+    for opts in (dict(), dict(split_min_samples=3072, units_per_group=16)):
+        print(f"  options {opts}", flush=True)
+        o = bns.bns_options_default(**opts)
+        outs = bns.bns_pc_skeleton_batch(handles, [d.alpha for d in dss],
+                                         [d.max_depth for d in dss], o)
+        assert len(outs) == len(dss)
+        for i, (got, g) in enumerate(zip(outs, gold)):
+            adj_ok = compare_adj_only(got, g)
+            assert adj_ok, f"cfg5[{i}] {opts}"
 
 
 def compare_adj_only(got, g):
