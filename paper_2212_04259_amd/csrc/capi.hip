@@ -132,7 +132,7 @@ struct DevCtx {
     hipStream_t stream = nullptr;
     std::mutex mu;
     // skeleton search
-    DevBuf setup, adj, nbr, deg, rowcnt, rowbase, edges_tmp, edges, min_accept, rdepth, pool, ctl;
+    DevBuf setup, adj, nbr, ipos, deg, rowcnt, rowbase, edges_tmp, edges, min_accept, rdepth, pool, ctl;
     // merge tables and chunk counters of split depths: all zero between tests
     DevBuf split_tab, split_cnt;
     bool split_dirty = false;
@@ -527,7 +527,7 @@ static bns_status dev_error(int32_t e) {
     }
 }
 
-static const int kDepthsPerLaunch = 4;
+static const int kDepthsPerLaunch = 8;
 // Split depths: merge tables (words) shared by a depth's tickets, the largest
 // ticket count that is split, and default chunk / occupancy targets.
 static const int64_t kSplitWords = 8 << 20;
@@ -618,6 +618,7 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     HIP_TRY(hipMemcpyAsync(dc.setup.p, dc.hpin, setup_bytes, hipMemcpyHostToDevice, s));
     HIP_TRY(dc.adj.ensure((size_t)adj_total));
     HIP_TRY(dc.nbr.ensure(sizeof(int32_t) * (size_t)adj_total));
+    HIP_TRY(dc.ipos.ensure(sizeof(int32_t) * (size_t)adj_total));
     HIP_TRY(dc.rdepth.ensure((size_t)adj_total));
     HIP_TRY(dc.deg.ensure(sizeof(int32_t) * (size_t)G));
     HIP_TRY(dc.rowcnt.ensure(sizeof(int32_t) * (size_t)G));
@@ -647,6 +648,7 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     a.pad = 0;
     a.adj = dc.adj.as<uint8_t>();
     a.nbr = dc.nbr.as<int32_t>();
+    a.ipos = dc.ipos.as<int32_t>();
     a.deg = dc.deg.as<int32_t>();
     a.rowcnt = dc.rowcnt.as<int32_t>();
     a.rowbase = dc.rowbase.as<int64_t>();

@@ -20,6 +20,7 @@ struct DepthArgs {
     int32_t pad;
     uint8_t *adj;             // per problem n*n block at adj_off
     int32_t *nbr;             // frozen adjacency lists, same blocks as adj
+    int32_t *ipos;            // ipos[v * n + u] = position of u in the frozen list of v
     int32_t *deg;             // per global variable
     int32_t *rowcnt;          // per global variable: alive edges (v, u > v)
     int64_t *rowbase;         // exclusive scan of rowcnt

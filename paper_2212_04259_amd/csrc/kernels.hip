@@ -84,32 +84,42 @@ __global__ void k_init_search(DepthArgs A) {
 
 // One wave per variable: freeze a(v) (ascending), its size, and the number of
 // surviving edges (v, u) with u > v.
-BNS_INLINE void snapshot_row(const DepthArgs &A, int g) {
+BNS_INLINE void snapshot_row(const DepthArgs &A, int g, int &deg_out, int &hi_out) {
     const int lane = threadIdx.x & 63;
     const ProbDev &P = A.probs[A.var2prob[g]];
     const int v = g - P.var_off, n = P.n;
     const uint8_t *row = A.adj + P.adj_off + (int64_t)v * n;
     int32_t *nb = A.nbr + P.adj_off + (int64_t)v * n;
+    int32_t *ip = A.ipos + P.adj_off + (int64_t)v * n;
     const uint64_t lt = lanes_below_mask();
     int cnt = 0, hi = 0;
     for (int u0 = 0; u0 < n; u0 += 64) {
         const int u = u0 + lane;
         const bool a = (u < n) && row[u];
         const uint64_t mask = __ballot(a);
-        if (a) nb[cnt + __popcll(mask & lt)] = u;
+        if (a) {
+            const int pos = cnt + __popcll(mask & lt);
+            nb[pos] = u;
+            ip[u] = pos;
+        }
         cnt += __popcll(mask);
         hi += __popcll(__ballot(a && u > v));
     }
-    if (lane == 0) {
-        A.deg[g] = cnt;
-        A.rowcnt[g] = hi;
-    }
+    deg_out = cnt;
+    hi_out = hi;
 }
 
 __global__ __launch_bounds__(kWG) void k_snapshot(DepthArgs A) {
     if (A.ctl->done) return;
     const int g = blockIdx.x * kWaves + (threadIdx.x >> 6);
-    if (g < A.n_globals) snapshot_row(A, g);
+    if (g < A.n_globals) {
+        int dg, hi;
+        snapshot_row(A, g, dg, hi);
+        if ((threadIdx.x & 63) == 0) {
+            A.deg[g] = dg;
+            A.rowcnt[g] = hi;
+        }
+    }
 }
 
 // Single workgroup: exclusive scan of the per-variable edge counts, reset of
@@ -203,16 +213,7 @@ BNS_INLINE void edges_row(const DepthArgs &A, Ctl *c, int g, unsigned int *hist)
             e.pA = dv - 1;
             e.pB = du - 1;
             e.posi = 0;
-            if (nB > 0) {
-                // position of v in the ascending list a(u)
-                const int32_t *nbu = A.nbr + P.adj_off + (int64_t)u * n;
-                int lo = 0, hi2 = du;
-                while (lo < hi2) {
-                    const int mid = (lo + hi2) >> 1;
-                    if (nbu[mid] < v) lo = mid + 1; else hi2 = mid;
-                }
-                e.posi = lo;
-            }
+            if (nB > 0) e.posi = A.ipos[P.adj_off + (int64_t)u * n + v];  // v in a(u)
             e.levels = ntot ? 64 - __clzll(ntot) : 0;
             atomicAdd(&hist[e.levels], 1u);
             A.edges_tmp[base + hi + __popcll(mhi & lt)] = e;
@@ -241,7 +242,8 @@ __global__ __launch_bounds__(kWG) void k_edges(DepthArgs A) {
 // Tickets per test wave from which one test per wave beats one per workgroup.
 constexpr unsigned long long kWaveModeRounds = 6;
 
-BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist) {
+BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist, int d,
+                            unsigned int *cursor_lds = nullptr, int *done_lds = nullptr) {
     const int lane = threadIdx.x & 63;
     // cursor[lv] = number of edges with more than lv levels (bucket start in
     // the descending order); lanes hold lv = lane and lv = 64, 65 go to lane 0.
@@ -258,6 +260,13 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
     if (lane == 0) {
         c->cursor[kMaxLevels + 1] = 0;
         c->cursor[kMaxLevels] = hist[kMaxLevels + 1];
+    }
+    if (cursor_lds) {
+        cursor_lds[lane] = start;
+        if (lane == 0) {
+            cursor_lds[kMaxLevels + 1] = 0;
+            cursor_lds[kMaxLevels] = hist[kMaxLevels + 1];
+        }
     }
     // level L (= lane): cnt = edges with levels > L, tickets cnt * 2^L
     const unsigned long long cnt = start;
@@ -280,7 +289,6 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
     if (lane == 0) {
         c->level_base[kMaxLevels] = total;
         c->level_cnt[kMaxLevels] = 0;
-        const int d = c->depth;
         if (any_bad) c->error = kDevTooManyTests;
         c->total_tickets = any_bad ? 0ull : total;
         c->ticket_ctr = 0;
@@ -325,6 +333,7 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
         // work for several rounds.
         const unsigned long long per = total * C / (4ull * groups);
         c->batch = (int)max(1ull, min(per, (unsigned long long)kSlotsPerWave));
+        if (done_lds) *done_lds = (total == 0 || any_bad) ? 1 : 0;
         if (total == 0 || any_bad) {
             c->done = 1;
         } else if (d < kMaxDepths) {
@@ -337,7 +346,7 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
 __global__ void k_levels(DepthArgs A) {
     Ctl *c = A.ctl;
     if (c->done) return;
-    levels_wave(A, c, c->hist);
+    levels_wave(A, c, c->hist, c->depth);
 }
 
 // Scatter into level order and reset the per-edge first-accept ranks.  The
@@ -382,63 +391,177 @@ __global__ __launch_bounds__(kWG) void k_scatter(DepthArgs A) {
                   (unsigned long long)gridDim.x * kWG);
 }
 
-// All preparation steps of a depth in one workgroup, for searches with at
-// most kSmallRows variables and kSmallPairs pairs: frozen adjacency lists,
-// edge records, ticket levels and level order.
+// ---------------------------------------------------------------------------
+// Small searches (at most kSmallRows variables and kSmallPairs pairs in all):
+// one workgroup prepares a depth (k_prepare_small, first depth) or removes
+// the accepted edges of a depth and prepares the next (k_apply_small), with
+// the per-variable state in LDS.  Edge records go straight to their slot in
+// the level order (a first pass over the rows counts the levels, a second
+// writes the records).
+// ---------------------------------------------------------------------------
 constexpr int kSmallThreads = 1024;
+constexpr int kSmallWaves = kSmallThreads / 64;
 constexpr int kSmallRows = 1024;
 constexpr int64_t kSmallPairs = 65536;
 
-__global__ __launch_bounds__(kSmallThreads) void k_prepare_small(DepthArgs A) {
-    Ctl *c = A.ctl;
-    if (c->done) return;
-    __shared__ unsigned int hist[kMaxLevels + 2];
-    __shared__ int64_t wsum[kSmallThreads / 64];
-    __shared__ int wmax[kSmallThreads / 64];
-    const int nw = kSmallThreads / 64, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+struct SmallSh {
+    uint64_t bcol[kSmallRows];  // C(x, d) for x <= max degree
+    int deg[kSmallRows];
+    int rowcnt[kSmallRows];
+    unsigned int hist[kMaxLevels + 2];
+    unsigned int cursor[kMaxLevels + 2];
+    unsigned long long red[2][kSmallWaves];
+    int wmax[kSmallWaves];
+    int done;
+};
+
+// Tests of edge (v, u) at depth d from the frozen degrees (0 when the depth
+// is beyond the problem's max_depth); sets an error for impossible counts.
+BNS_INLINE void small_counts(Ctl *c, const SmallSh &sh, bool depth_ok, int d, int dv, int du,
+                             uint64_t &nA, uint64_t &nB) {
+    nA = nB = 0;
+    if (!depth_ok) return;
+    if (d == 0) {
+        nA = 1;
+    } else if (d > kMaxZ) {
+        if (dv - 1 >= d || du - 1 >= d) c->error = kDevDepthTooLarge;
+    } else {
+        nA = (dv >= 1) ? sh.bcol[dv - 1] : 0;
+        nB = (du >= 1) ? sh.bcol[du - 1] : 0;
+    }
+    if (nA + nB > (1ull << 40)) {
+        c->error = kDevTooManyTests;
+        nA = nB = 0;
+    }
+}
+
+BNS_INLINE void prepare_block(const DepthArgs &A, Ctl *c, int d, SmallSh &sh) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int G = A.n_globals;
-    for (int i = threadIdx.x; i < kMaxLevels + 2; i += kSmallThreads) hist[i] = 0;
-    for (int g = w; g < G; g += nw) snapshot_row(A, g);
+    for (int i = threadIdx.x; i < kMaxLevels + 2; i += kSmallThreads) sh.hist[i] = 0;
+    // frozen adjacency lists, degrees and higher-neighbour counts
+    for (int g = w; g < G; g += kSmallWaves) {
+        int dg, hi;
+        snapshot_row(A, g, dg, hi);
+        if (lane == 0) {
+            sh.deg[g] = dg;
+            sh.rowcnt[g] = hi;
+        }
+    }
     __syncthreads();
-    // exclusive scan of the per-variable edge counts (one variable per thread)
-    const int g0 = threadIdx.x;
-    const int64_t mine = (g0 < G) ? A.rowcnt[g0] : 0;
-    const int md = (g0 < G) ? A.deg[g0] : 0;
-    int64_t inc = mine;
-    int mx = md;
+    // edge total and largest degree
+    {
+        int64_t s = 0;
+        int md = 0;
+        for (int g = threadIdx.x; g < G; g += kSmallThreads) {
+            s += sh.rowcnt[g];
+            md = max(md, sh.deg[g]);
+        }
+        s = wave_sum(s);
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int64_t o = __shfl_up(inc, off, 64);
-        const int om = __shfl_xor(mx, off, 64);
-        if (lane >= off) inc += o;
-        mx = max(mx, om);
+        for (int off = 32; off > 0; off >>= 1) md = max(md, __shfl_xor(md, off, 64));
+        if (lane == 0) {
+            sh.red[0][w] = (unsigned long long)s;
+            sh.wmax[w] = md;
+        }
     }
-    if (lane == 63) wsum[w] = inc;
-    if (lane == 0) wmax[w] = mx;
     __syncthreads();
-    int64_t before = 0, total = 0;
     int maxdeg = 0;
-    for (int i = 0; i < nw; ++i) {
-        if (i < w) before += wsum[i];
-        total += wsum[i];
-        maxdeg = max(maxdeg, wmax[i]);
+    unsigned long long E = 0;
+    for (int i = 0; i < kSmallWaves; ++i) {
+        E += sh.red[0][i];
+        maxdeg = max(maxdeg, sh.wmax[i]);
     }
-    if (g0 < G) A.rowbase[g0] = before + inc - mine;
+    for (int x = threadIdx.x; x <= maxdeg && d <= kMaxZ; x += kSmallThreads)
+        sh.bcol[x] = binom_at(A.binom, A.binom_rows, x, d);
     if (threadIdx.x == 0) {
-        c->n_edges = (unsigned long long)total;
+        c->n_edges = E;
         c->maxdeg = maxdeg;
         c->ticket_ctr = 0;
         c->total_tickets = 0;
-        if (c->depth >= kMaxDepths) c->error = kDevDepthTooLarge;
+        if (d >= kMaxDepths) c->error = kDevDepthTooLarge;
     }
     __syncthreads();
-    for (int g = w; g < G; g += nw)
-        if (A.rowcnt[g] > 0) edges_row(A, c, g, hist);
+    // pass 1: level histogram
+    for (int g = w; g < G; g += kSmallWaves) {
+        if (sh.rowcnt[g] == 0) continue;
+        const ProbDev &P = A.probs[A.var2prob[g]];
+        const int v = g - P.var_off, n = P.n;
+        const bool depth_ok = (P.max_depth < 0 || d <= P.max_depth);
+        const uint8_t *row = A.adj + P.adj_off + (int64_t)v * n;
+        const int dv = sh.deg[g];
+        for (int u = v + 1 + lane; u < n; u += 64) {
+            if (!row[u]) continue;
+            uint64_t nA, nB;
+            small_counts(c, sh, depth_ok, d, dv, sh.deg[P.var_off + u], nA, nB);
+            const uint64_t nt = nA + nB;
+            atomicAdd(&sh.hist[nt ? 64 - __clzll(nt) : 0], 1u);
+        }
+    }
     __syncthreads();
-    if (w == 0) levels_wave(A, c, hist);
+    if (w == 0) levels_wave(A, c, sh.hist, d, sh.cursor, &sh.done);
     __syncthreads();
+    if (sh.done) return;
+    // pass 2: edge records in level order
+    const uint64_t lt = lanes_below_mask();
+    for (int g = w; g < G; g += kSmallWaves) {
+        if (sh.rowcnt[g] == 0) continue;
+        const int pi = A.var2prob[g];
+        const ProbDev &P = A.probs[pi];
+        const int v = g - P.var_off, n = P.n;
+        const bool depth_ok = (P.max_depth < 0 || d <= P.max_depth);
+        const uint8_t *row = A.adj + P.adj_off + (int64_t)v * n;
+        const int dv = sh.deg[g];
+        int cnt = 0;
+        for (int u0 = 0; u0 < n; u0 += 64) {
+            const int u = u0 + lane;
+            const bool a = (u < n) && row[u];
+            const uint64_t mask = __ballot(a);
+            const bool take = a && u > v;
+            EdgeRec e;
+            int lv = -1;
+            if (take) {
+                const int du = sh.deg[P.var_off + u];
+                uint64_t nA, nB;
+                small_counts(c, sh, depth_ok, d, dv, du, nA, nB);
+                e.prob = pi;
+                e.i = v;
+                e.j = u;
+                e.posj = cnt + __popcll(mask & lt);
+                e.posi = (nB > 0) ? A.ipos[P.adj_off + (int64_t)u * n + v] : 0;
+                e.pA = dv - 1;
+                e.pB = du - 1;
+                e.nA = nA;
+                e.n = nA + nB;
+                e.levels = e.n ? 64 - __clzll(e.n) : 0;
+                lv = e.levels;
+            }
+            cnt += __popcll(mask);
+            uint64_t todo = __ballot(take);
+            unsigned int pos = 0;
+            while (todo) {
+                const int leader = __ffsll((long long)todo) - 1;
+                const int L = __shfl(lv, leader, 64);
+                const uint64_t same = __ballot(take && lv == L);
+                unsigned int b = 0;
+                if (lane == leader) b = atomicAdd(&sh.cursor[L], (unsigned int)__popcll(same));
+                b = __shfl(b, leader, 64);
+                if (take && lv == L) pos = b + (unsigned int)__popcll(same & lt);
+                todo &= ~same;
+            }
+            if (take) {
+                A.edges[pos] = e;
+                A.min_accept[pos] = ~0ull;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kSmallThreads) void k_prepare_small(DepthArgs A) {
+    __shared__ SmallSh sh;
+    Ctl *c = A.ctl;
     if (c->done) return;
-    scatter_edges(A, c, (unsigned long long)w * 64, (unsigned long long)kSmallThreads);
+    prepare_block(A, c, c->depth, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -539,28 +662,28 @@ BNS_INLINE void decode_ticket(const DepthArgs &A, const unsigned long long *lvl_
         unrank_lane(btab, bstride, brows, p, d, sideA ? r : r - rec.nA, q.var + 2);
         // positions -> variable ids, up to 8 loads in flight at a time
         const int32_t *nbo = A.nbr + P.adj_off + (int64_t)owner * P.n;
+        // (unconditional loads at a clamped, always valid position, so that
+        // all of them are in flight together)
         for (int k0 = 0; k0 < d; k0 += 8) {
-            uint16_t vv[8];
+            uint32_t vv[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int pos = (k0 + k < d) ? q.var[2 + k0 + k] : 0;
+                vv[k] = (uint32_t)nbo[pos + (pos >= skip ? 1 : 0)];
+            }
 #pragma unroll
             for (int k = 0; k < 8; ++k)
-                if (k0 + k < d) {
-                    const int pos = q.var[2 + k0 + k];
-                    vv[k] = (uint16_t)nbo[pos + (pos >= skip ? 1 : 0)];
-                }
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-                if (k0 + k < d) q.var[2 + k0 + k] = vv[k];
+                if (k0 + k < d) q.var[2 + k0 + k] = (uint16_t)vv[k];
         }
     }
     const uint8_t *cards = A.cards + P.var_off;
     for (int k0 = 0; k0 < d + 2; k0 += 8) {
-        uint8_t cc[8];
+        uint32_t cc[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) cc[k] = cards[(k0 + k < d + 2) ? q.var[k0 + k] : 0];
 #pragma unroll
         for (int k = 0; k < 8; ++k)
-            if (k0 + k < d + 2) cc[k] = cards[q.var[k0 + k]];
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-            if (k0 + k < d + 2) q.card[k0 + k] = cc[k];
+            if (k0 + k < d + 2) q.card[k0 + k] = (uint8_t)cc[k];
     }
 }
 
@@ -753,19 +876,17 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
 // test count (per edge: ranks up to and including its first accepting one).
 // The last block to finish advances the control block to the next depth.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kWG) void k_apply(DepthArgs A) {
-    Ctl *c = A.ctl;
-    if (c->done) return;
-    __shared__ unsigned long long red[2][kWaves];
-    const int d = c->depth;
+// Removals of edges [first, E) in steps of stride (per wave): accepted edges
+// leave the graph; the canonical test count and removals are tallied into
+// req and rem.  Removal records of depth >= 1 go to the pool, densely:
+// [problem, i, j, s_1 .. s_d] (d + 3 words), one atomic per wave.
+BNS_INLINE void apply_edges(const DepthArgs &A, Ctl *c, int d, unsigned long long first,
+                            unsigned long long stride, unsigned long long &req,
+                            unsigned long long &rem) {
     const unsigned long long E = c->n_edges;
     const int lane = threadIdx.x & 63;
     const uint64_t lt = lanes_below_mask();
-    unsigned long long req = 0, rem = 0;
-    // Removal records of depth >= 1 go to the pool, densely:
-    // [problem, i, j, s_1 .. s_d] (d + 3 words), one atomic per wave.
-    for (unsigned long long base = (unsigned long long)blockIdx.x * kWG + (threadIdx.x & ~63u);
-         base < E; base += (unsigned long long)gridDim.x * kWG) {
+    for (unsigned long long base = first; base < E; base += stride) {
         const unsigned long long e = base + lane;
         const bool valid = e < E;
         EdgeRec r;
@@ -813,6 +934,18 @@ __global__ __launch_bounds__(kWG) void k_apply(DepthArgs A) {
         A.rdepth[ij] = (int8_t)d;
         A.rdepth[ji] = (int8_t)d;
     }
+}
+
+// Depth completion over many workgroups; the last one to finish advances
+// the control block to the next depth.
+__global__ __launch_bounds__(kWG) void k_apply(DepthArgs A) {
+    Ctl *c = A.ctl;
+    if (c->done) return;
+    __shared__ unsigned long long red[2][kWaves];
+    const int d = c->depth;
+    unsigned long long req = 0, rem = 0;
+    apply_edges(A, c, d, (unsigned long long)blockIdx.x * kWG + (threadIdx.x & ~63u),
+                (unsigned long long)gridDim.x * kWG, req, rem);
     req = wave_sum(req);
     rem = wave_sum(rem);
     if ((threadIdx.x & 63) == 0) {
@@ -840,21 +973,60 @@ __global__ __launch_bounds__(kWG) void k_apply(DepthArgs A) {
     }
 }
 
+// Small searches: completion of depth d and preparation of depth d + 1 in
+// one workgroup (the adjacency updates are visible to the whole workgroup
+// after the barrier).
+__global__ __launch_bounds__(kSmallThreads) void k_apply_small(DepthArgs A) {
+    __shared__ SmallSh sh;
+    Ctl *c = A.ctl;
+    if (c->done) return;
+    const int d = c->depth;
+    const int w = threadIdx.x >> 6;
+    unsigned long long req = 0, rem = 0;
+    apply_edges(A, c, d, (unsigned long long)w * 64, (unsigned long long)kSmallThreads, req, rem);
+    req = wave_sum(req);
+    rem = wave_sum(rem);
+    if ((threadIdx.x & 63) == 0) {
+        sh.red[0][w] = req;
+        sh.red[1][w] = rem;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long a = 0, b = 0;
+        for (int i = 0; i < kSmallWaves; ++i) {
+            a += sh.red[0][i];
+            b += sh.red[1][i];
+        }
+        if (d < kMaxDepths) {
+            c->stats[d].required += a;
+            c->stats[d].removed += b;
+        }
+        c->depth = d + 1;
+    }
+    __syncthreads();
+    prepare_block(A, c, d + 1, sh);
+}
+
 // ---------------------------------------------------------------------------
 // Launchers of the depth pipeline
 // ---------------------------------------------------------------------------
 static int grid_rows(int n_globals) { return (n_globals + kWaves - 1) / kWaves; }
 
+static bool small_search(const DepthArgs &a) {
+    return a.n_globals <= kSmallRows && a.n_pairs <= kSmallPairs;
+}
+
+// Small searches prepare depth 0 here and every later depth in the removal
+// kernel of the depth before; larger ones prepare each depth in
+// launch_depth_prepare.
 hipError_t launch_init_search(const DepthArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_init_search, dim3(64, a.n_probs), dim3(kWG), 0, s, a);
+    if (small_search(a)) hipLaunchKernelGGL(k_prepare_small, dim3(1), dim3(kSmallThreads), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_depth_prepare(const DepthArgs &a, hipStream_t s) {
-    if (a.n_globals <= kSmallRows && a.n_pairs <= kSmallPairs) {
-        hipLaunchKernelGGL(k_prepare_small, dim3(1), dim3(kSmallThreads), 0, s, a);
-        return hipGetLastError();
-    }
+    if (small_search(a)) return hipSuccess;
     const int gr = grid_rows(a.n_globals);
     hipLaunchKernelGGL(k_snapshot, dim3(gr), dim3(kWG), 0, s, a);
     hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(kWG), 0, s, a);
@@ -870,7 +1042,8 @@ hipError_t launch_depth_tests(const DepthArgs &a, int grid, hipStream_t s) {
 }
 
 hipError_t launch_depth_apply(const DepthArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_apply, dim3(a.edge_grid), dim3(kWG), 0, s, a);
+    if (small_search(a)) hipLaunchKernelGGL(k_apply_small, dim3(1), dim3(kSmallThreads), 0, s, a);
+    else hipLaunchKernelGGL(k_apply, dim3(a.edge_grid), dim3(kWG), 0, s, a);
     return hipGetLastError();
 }
 
