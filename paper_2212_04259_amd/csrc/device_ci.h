@@ -310,6 +310,80 @@ BNS_INLINE const gvec4 *uniform_col(const uint8_t *p) {
     return (const gvec4 *)(((uint64_t)hi << 32) | lo);
 }
 
+// LDS byte offset of a pointer into LDS, and an increment of the LDS word at
+// a byte offset.
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+BNS_INLINE uint32_t lds_offset(const uint32_t *p) { return (uint32_t)(uintptr_t)(const lds_u32 *)p; }
+BNS_INLINE void lds_inc(uint32_t byte_off) {
+    __atomic_fetch_add((lds_u32 *)(uintptr_t)byte_off, 1u, __ATOMIC_RELAXED);
+}
+
+// Two samples per register: bytes 0 and 2 (or 1 and 3) of a column word are
+// moved into the two 16-bit halves, and one 24-bit multiply-add per column
+// advances both samples' LDS byte addresses, base + 4 (R cell + replica).
+// mul4[k] = 4 R mult_k and base2 holds base + 4 replica in both halves;
+// every address stays below 2^16, so the halves never carry into each other.
+// NC + 1 vector operations per sample instead of 2 NC + 1.
+BNS_INLINE uint32_t mad24(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t d;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "s"(b), "v"(c));
+    return d;
+}
+
+template <int NC>
+BNS_INLINE void count16_packed(const u32x4 (&v)[NC], const uint32_t (&mul4)[NC], uint32_t base2) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        uint32_t lo = base2, hi = base2;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const uint32_t w = v[k][j];
+            lo = mad24(__builtin_amdgcn_perm(0u, w, 0x0c020c00u), mul4[k], lo);  // samples 0, 2
+            hi = mad24(__builtin_amdgcn_perm(0u, w, 0x0c030c01u), mul4[k], hi);  // samples 1, 3
+        }
+        lds_inc(lo & 0xffffu);
+        lds_inc(lo >> 16);
+        lds_inc(hi & 0xffffu);
+        lds_inc(hi >> 16);
+    }
+}
+
+// Single-pass counting of the groups of 16 samples [q0, q1) into a
+// replicated table whose byte addresses lie below 2^16.
+template <int NC>
+BNS_INLINE void count_packed(const TestSh &t, uint32_t *tab, int logR, int64_t q0, int64_t q1,
+                             int rank, int S) {
+    constexpr int U = (NC <= 3) ? 4 : 2;
+    const uint32_t rep = (uint32_t)rank & ((1u << logR) - 1u);
+    const uint32_t b = lds_offset(tab) + 4u * rep;
+    const uint32_t base2 = b | (b << 16);
+    const gvec4 *cp[NC];
+    uint32_t mul4[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        cp[k] = uniform_col(t.col[k]) + q0;
+        mul4[k] = __builtin_amdgcn_readfirstlane(t.mult[k] << (logR + 2));
+    }
+    const uint32_t n = (uint32_t)(q1 - q0);
+    const uint32_t us = (uint32_t)S;
+    uint32_t i = (uint32_t)rank;
+    for (; i + (U - 1) * us < n; i += U * us) {
+        u32x4 v[U][NC];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < NC; ++k) v[u][k] = cp[k][i + u * us];
+#pragma unroll
+        for (int u = 0; u < U; ++u) count16_packed<NC>(v[u], mul4, base2);
+    }
+    for (; i < n; i += us) {
+        u32x4 v[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) v[k] = cp[k][i];
+        count16_packed<NC>(v, mul4, base2);
+    }
+}
+
 template <int NC, bool kChunk>
 BNS_INLINE void count16(const u32x4 (&v)[NC], const uint32_t (&mul)[NC], uint32_t *tab,
                         uint32_t cbase, uint32_t Tc, uint32_t trash, int logR, uint32_t rep,
@@ -424,13 +498,30 @@ template <bool kChunk>
 BNS_INLINE void count_range(const TestSh &t, uint32_t *tab, uint32_t cbase, uint32_t Tc,
                             uint32_t trash, int logR, int64_t s0, int64_t s1, int rank, int S) {
     const int64_t q0 = s0 >> 4, q1 = s1 >> 4;
-    switch (t.ncols) {
-        case 2: count_fixed<2, kChunk>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
-        case 3: count_fixed<3, kChunk>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
-        case 4: count_fixed<4, kChunk>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
-        case 5: count_fixed<5, kChunk>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
-        case 6: count_fixed<6, kChunk>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
-        default: count_generic<kChunk>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
+    const int nc = uni(t.ncols);
+    if (!kChunk) {
+        // packed path when every byte address of the replicated table fits 16 bits
+        const bool packed = nc <= 6 && (uint64_t)lds_offset(tab) + 4ull * ((uint64_t)Tc << logR) <= 65536ull;
+        if (packed) {
+            switch (nc) {
+                case 2: count_packed<2>(t, tab, logR, q0, q1, rank, S); break;
+                case 3: count_packed<3>(t, tab, logR, q0, q1, rank, S); break;
+                case 4: count_packed<4>(t, tab, logR, q0, q1, rank, S); break;
+                case 5: count_packed<5>(t, tab, logR, q0, q1, rank, S); break;
+                default: count_packed<6>(t, tab, logR, q0, q1, rank, S); break;
+            }
+        } else {
+            count_generic<false>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S);
+        }
+    } else {
+        switch (nc) {
+            case 2: count_fixed<2, true>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
+            case 3: count_fixed<3, true>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
+            case 4: count_fixed<4, true>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
+            case 5: count_fixed<5, true>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
+            case 6: count_fixed<6, true>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
+            default: count_generic<true>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
+        }
     }
     if ((q1 << 4) < s1) count_tail<kChunk>(t, tab, cbase, Tc, trash, logR, q1 << 4, s1, rank, S);
 }
@@ -520,8 +611,11 @@ struct Plan {
 };
 
 // W: LDS words available to the group; S: lanes in the group; msamp: samples
-// the group counts (replication must stay cheap against them).
-BNS_INLINE Plan make_plan(const TestSh &t, uint32_t W, int max_rep_log2, int S, int64_t msamp) {
+// the group counts (replication must stay cheap against them); addr_words:
+// words of the slice below LDS byte 2^16 (replication stops there so that
+// single-pass counting can use 16-bit addresses).
+BNS_INLINE Plan make_plan(const TestSh &t, uint32_t W, int max_rep_log2, int S, int64_t msamp,
+                          uint32_t addr_words) {
     Plan P;
     P.err = kDevOk;
     P.rx = uni(t.card[0]);
@@ -552,6 +646,7 @@ BNS_INLINE Plan make_plan(const TestSh &t, uint32_t W, int max_rep_log2, int S, 
         while (P.logR < max_rep_log2) {
             const uint64_t R2 = 2ull << P.logR;
             if ((uint64_t)P.T * R2 + P.T + marg > W) break;
+            if ((uint64_t)P.T * R2 > addr_words) break;
             if ((int64_t)(P.T * R2) * 4 > m + 16 * S) break;
             ++P.logR;
         }
@@ -694,7 +789,10 @@ BNS_INLINE TestOut run_test(const Grp &g, TestSh &t, uint32_t *lds, uint32_t W, 
                             double alpha, uint32_t *gtab, const Src &src) {
     TestOut o;
     o.flags = 0;
-    const Plan P = make_plan(t, W, src.gsrc ? 0 : tile.max_rep_log2, g.size, src.s1 - src.s0);
+    const uint32_t lo = lds_offset(lds);
+    const uint32_t addr_words = lo < 65536u ? (65536u - lo) / 4u : 0u;
+    const Plan P = make_plan(t, W, src.gsrc ? 0 : tile.max_rep_log2, g.size, src.s1 - src.s0,
+                             addr_words);
     o.err = P.err;
     o.df = P.df;
     if (P.err != kDevOk) {

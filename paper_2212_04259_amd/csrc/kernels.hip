@@ -597,7 +597,9 @@ struct Desc {
     uint8_t card[kMaxCols];
 };
 
-constexpr int kBinomLds = 512;  // binomial entries staged in LDS
+constexpr int kBinomLds = 512;   // binomial entries staged in LDS
+constexpr int kProbsLds = 8;     // problem records staged in LDS (searches of few problems)
+constexpr int kCardsLds = 2048;  // cardinalities staged in LDS (searches of few variables)
 
 BNS_INLINE uint64_t bnm(const uint64_t *tab, int stride, int rows, int64_t n, int k) {
     if (n < 0 || k < 0 || k > n) return 0;
@@ -626,7 +628,7 @@ BNS_INLINE void unrank_lane(const uint64_t *tab, int stride, int rows, int64_t p
 BNS_INLINE void decode_ticket(const DepthArgs &A, const unsigned long long *lvl_base,
                               const unsigned long long *lvl_cnt, int nlev, unsigned long long tk,
                               int d, const uint64_t *btab, int bstride, int brows, bool skip_ok,
-                              Desc &q) {
+                              const ProbDev *probs_lds, const uint8_t *cards_lds, Desc &q) {
     int lo = 0, hi = nlev - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -644,7 +646,9 @@ BNS_INLINE void decode_ticket(const DepthArgs &A, const unsigned long long *lvl_
         __hip_atomic_load(&A.min_accept[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     q.valid = (r < rec.n && (!skip_ok || r <= ma)) ? 1 : 0;
     if (!q.valid) return;
-    const ProbDev P = A.probs[rec.prob];
+    ProbDev P;
+    if (probs_lds) P = probs_lds[rec.prob];
+    else P = A.probs[rec.prob];
     q.data = P.data;
     q.ld = P.ld;
     q.m = P.m;
@@ -675,6 +679,11 @@ BNS_INLINE void decode_ticket(const DepthArgs &A, const unsigned long long *lvl_
             for (int k = 0; k < 8; ++k)
                 if (k0 + k < d) q.var[2 + k0 + k] = (uint16_t)vv[k];
         }
+    }
+    if (cards_lds) {
+        const uint8_t *cards = cards_lds + P.var_off;
+        for (int k = 0; k < d + 2; ++k) q.card[k] = cards[q.var[k]];
+        return;
     }
     const uint8_t *cards = A.cards + P.var_off;
     for (int k0 = 0; k0 < d + 2; k0 += 8) {
@@ -725,6 +734,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
     __shared__ unsigned long long lvl_base[kMaxLevels + 1];
     __shared__ unsigned long long lvl_cnt[kMaxLevels + 1];
     __shared__ uint64_t btab_lds[kBinomLds];
+    __shared__ ProbDev probs_sh[kProbsLds];
+    __shared__ uint8_t cards_sh[kCardsLds];
     __shared__ unsigned long long grab;
     // per-group tallies (kept in LDS: no vector registers across tests)
     __shared__ unsigned long long tal_exec[kWaves], tal_re[kWaves];
@@ -748,6 +759,13 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
         lvl_base[threadIdx.x] = c->level_base[threadIdx.x];
         lvl_cnt[threadIdx.x] = c->level_cnt[threadIdx.x];
     }
+    // problem records and cardinalities in LDS when they fit (two fewer
+    // dependent loads per ticket decode)
+    const bool probs_in_lds = A.n_probs <= kProbsLds;
+    const bool cards_in_lds = A.n_globals <= kCardsLds;
+    if (probs_in_lds && threadIdx.x < (unsigned)A.n_probs) probs_sh[threadIdx.x] = A.probs[threadIdx.x];
+    if (cards_in_lds)
+        for (int i = threadIdx.x; i < A.n_globals; i += kWG) cards_sh[i] = A.cards[i];
     // binomials C(n, k), n <= max degree, k <= d: in LDS when they fit
     const int brows_need = c->maxdeg + 1;
     const uint64_t *btab = A.binom;
@@ -775,9 +793,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int ti = mode ? 0 : w;  // tally slot of the group
     // A unit is (ticket, chunk); chunk-major order puts the chunks of one
     // ticket far apart, so they run on different groups at the same time.
+    unsigned long long base = 0;
+    if (g.rank == 0) base = atomicAdd(&c->ticket_ctr, (unsigned long long)B);
     for (;;) {
-        unsigned long long base = 0;
-        if (g.rank == 0) base = atomicAdd(&c->ticket_ctr, (unsigned long long)B);
         if (mode) {
             if (threadIdx.x == 0) grab = base;
             __syncthreads();
@@ -793,7 +811,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
             const unsigned long long ch = (C > 1) ? u / total : 0ull;
             const unsigned long long tk = u - ch * total;
             Desc &q = mine[g.rank];
-            decode_ticket(A, lvl_base, lvl_cnt, nlev, tk, d, btab, bstride, brows, C == 1, q);
+            decode_ticket(A, lvl_base, lvl_cnt, nlev, tk, d, btab, bstride, brows, C == 1,
+                          probs_in_lds ? probs_sh : nullptr, cards_in_lds ? cards_sh : nullptr, q);
             q.tk = tk;
             q.chunk = (int32_t)ch;
         }
@@ -861,6 +880,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
             }
             g.sync();
         }
+        base = 0;
+        if (g.rank == 0) base = atomicAdd(&c->ticket_ctr, (unsigned long long)B);
     }
     __syncthreads();
     if (threadIdx.x < kWaves && d < kMaxDepths) {
