@@ -97,7 +97,11 @@ typedef struct bns_options {
                               lanes; 0 = default (1) */
     int32_t test_group;    /* batched form: lanes that run one test: 0 = automatic,
                               1 = one wave (64 lanes), 2 = one workgroup (256 lanes) */
-    int32_t reserved[5];   /* must be zero */
+    int32_t max_replicas;  /* copies of a contingency table in LDS that lanes increment
+                              (summed before G^2); a power of two in [1, 64]; 0 = default */
+    int32_t tickets_per_grab; /* batched form: tests taken per grab of the shared ticket
+                              counter, in [1, 8]; 0 = automatic */
+    int32_t reserved[3];   /* must be zero */
     void *stream;          /* hipStream_t; NULL = default stream */
 } bns_options;
 

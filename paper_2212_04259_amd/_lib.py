@@ -46,7 +46,8 @@ class bns_options(ctypes.Structure):
                 ("wg_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("split_min_samples", ctypes.c_int32),
                 ("units_per_group", ctypes.c_int32), ("test_group", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5),
+                ("max_replicas", ctypes.c_int32), ("tickets_per_grab", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3),
                 ("stream", ctypes.c_void_p)]
 
 

@@ -80,7 +80,12 @@ static bns_status read_options(const bns_options *in, bns_options *out) {
         return fail(BNS_E_INVALID_ARG, "options.units_per_group must be in [0, 1024]");
     if (out->test_group < 0 || out->test_group > 2)
         return fail(BNS_E_INVALID_ARG, "options.test_group must be 0, 1 or 2");
-    for (int i = 0; i < 5; ++i)
+    if (out->max_replicas < 0 || out->max_replicas > 64 ||
+        (out->max_replicas & (out->max_replicas - 1)) != 0)
+        return fail(BNS_E_INVALID_ARG, "options.max_replicas must be 0 or a power of two up to 64");
+    if (out->tickets_per_grab < 0 || out->tickets_per_grab > kSlotsPerWave)
+        return fail(BNS_E_INVALID_ARG, "options.tickets_per_grab must be in [0, %d]", kSlotsPerWave);
+    for (int i = 0; i < 3; ++i)
         if (out->reserved[i] != 0) return fail(BNS_E_INVALID_ARG, "options.reserved must be zero");
     return BNS_OK;
 }
@@ -325,7 +330,8 @@ static bns_status make_tile(const DevCtx &dc, const bns_options &o, Tile *t, boo
         if (e != hipSuccess) return fail(BNS_E_DEVICE, "cannot enable %d bytes of dynamic LDS: %s", lds, hipGetErrorString(e));
     }
     t->lds_words = lds / 4;
-    t->max_rep_log2 = 6;
+    t->max_rep_log2 = 5;  // 32 copies: fewer to clear and sum than 64, as fast to count
+    if (o.max_replicas > 0) t->max_rep_log2 = __builtin_ctz((unsigned)o.max_replicas);
     t->fp64 = (o.precision == BNS_PREC_FP64) ? 1 : 0;
     t->band = o.recheck_band;
     t->pad = 0;
@@ -667,6 +673,7 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     a.split_min = o.split_min_samples == 0 ? kSplitMinDefault : o.split_min_samples;
     a.units_per_group = o.units_per_group == 0 ? kUnitsPerGroupDefault : o.units_per_group;
     a.mode_policy = o.test_group;
+    a.grab_fixed = o.tickets_per_grab;
 
     const int lds_bytes = tile.lds_words * 4;
     int wg = o.wg_per_cu ? o.wg_per_cu : depth_tests_max_wg_per_cu(lds_bytes);

@@ -46,7 +46,7 @@ struct DepthArgs {
     int32_t split_min;        // smallest chunk in samples; <= 0 disables splitting
     int32_t units_per_group;  // work units aimed for per concurrent group when splitting
     int32_t mode_policy;      // 0 automatic, 1 one test per wave, 2 one test per workgroup
-    int32_t pad2;
+    int32_t grab_fixed;       // tickets per grab (0: from the ticket count)
 };
 
 hipError_t launch_depth_prepare(const DepthArgs &a, hipStream_t s);   // snapshot .. scatter

@@ -332,7 +332,8 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
         // Grabs of several units amortise the decode latency when there is
         // work for several rounds.
         const unsigned long long per = total * C / (4ull * groups);
-        c->batch = (int)max(1ull, min(per, (unsigned long long)kSlotsPerWave));
+        c->batch = A.grab_fixed > 0 ? A.grab_fixed
+                                    : (int)max(1ull, min(per, (unsigned long long)kSlotsPerWave));
         if (done_lds) *done_lds = (total == 0 || any_bad) ? 1 : 0;
         if (total == 0 || any_bad) {
             c->done = 1;
@@ -820,6 +821,15 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
         for (int j = 0; j < cnt; ++j) {
             const Desc &q = mine[j];
             if (!uni(q.valid)) continue;
+            // Lane 0 fetches the next test's current first-accept rank while
+            // this test runs and drops that test before it starts if a lower
+            // rank of its edge has accepted meanwhile (the check at decode is
+            // up to a batch old).  Split depths run every unit.
+            const bool chk = C == 1 && j + 1 < cnt && g.rank == 0 && mine[j + 1].valid;
+            unsigned long long ma_next = ~0ull;
+            if (chk)
+                ma_next = __hip_atomic_load(&A.min_accept[mine[j + 1].e], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
             stage_test(g, q, t);
             const int64_t qm = uni(q.m);
             // Split depths: unit (ticket, chunk) counts its chunk of samples
@@ -878,6 +888,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
                 }
                 break;
             }
+            if (chk && mine[j + 1].r > ma_next) mine[j + 1].valid = 0;
             g.sync();
         }
         base = 0;

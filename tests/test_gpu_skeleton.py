@@ -66,6 +66,8 @@ def test_plain_matches_golden(bns, k):
     dict(test_group=2), dict(test_group=2, split_min_samples=-1),
     dict(test_group=2, split_min_samples=1024, units_per_group=64),
     dict(test_group=1, split_min_samples=2048, units_per_group=4, precision=1),
+    dict(max_replicas=1), dict(max_replicas=16, tickets_per_grab=8),
+    dict(test_group=1, max_replicas=4, tickets_per_grab=1),
 ])
 def test_tile_shapes_and_modes_identical(bns, opts):
     g = load_golden(2)["datasets"][0]
