@@ -33,7 +33,7 @@ struct ProbDev {
     int64_t adj_off;      // offset of this problem's n*n block in adjacency / pair arrays
     double alpha;
     int32_t max_depth;    // -1: unbounded
-    int32_t pad;
+    int32_t bit_off;      // first word of this problem's adjacency bit rows (small searches)
 };
 
 // One surviving edge (i < j, local ids) at the current depth.

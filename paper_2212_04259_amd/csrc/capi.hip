@@ -137,7 +137,7 @@ struct DevCtx {
     hipStream_t stream = nullptr;
     std::mutex mu;
     // skeleton search
-    DevBuf setup, adj, nbr, ipos, deg, rowcnt, rowbase, edges_tmp, edges, min_accept, rdepth, pool, ctl;
+    DevBuf setup, adj, adjbits, nbr, ipos, deg, rowcnt, rowbase, edges_tmp, edges, min_accept, rdepth, pool, ctl;
     // merge tables and chunk counters of split depths: all zero between tests
     DevBuf split_tab, split_cnt;
     bool split_dirty = false;
@@ -159,6 +159,19 @@ struct DevCtx {
     }
     std::vector<std::unique_ptr<GraphEntry>> graphs;  // captured depth launches
     int search_lds = 0;  // default dynamic LDS of the skeleton test kernel (bytes)
+    int last_sequences = 0;  // depth sequences the last finished search needed
+    void *hres = nullptr;    // pinned staging for result downloads
+    size_t hres_bytes = 0;
+    hipError_t results(size_t n) {
+        if (n <= hres_bytes && hres) return hipSuccess;
+        if (hres) (void)hipHostFree(hres);
+        hres = nullptr;
+        hres_bytes = 0;
+        const size_t want = std::max<size_t>(n, 1 << 16);
+        hipError_t e = hipHostMalloc(&hres, want, hipHostMallocDefault);
+        if (e == hipSuccess) hres_bytes = want;
+        return e;
+    }
     int lds_per_cu = 0;
 };
 
@@ -540,6 +553,9 @@ static const int64_t kSplitWords = 8 << 20;
 static const int64_t kSplitTickets = 32768;
 static const int32_t kSplitMinDefault = 4096;
 static const int32_t kUnitsPerGroupDefault = 1;
+// Results downloaded with the control block after each launch when they fit.
+static const size_t kSpecBytes = 4u << 20;
+static const size_t kSpecPoolWords = 64u << 10;
 
 // Captures (once per distinct argument set) K consecutive depth sequences as
 // one executable graph; the depth index lives in the device control block, so
@@ -584,12 +600,14 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     std::vector<ProbDev> probs((size_t)P);
     std::vector<int32_t> var2prob;
     std::vector<uint8_t> gcards;
-    int64_t adj_total = 0, pairs_total = 0, m_max = 1;
+    int64_t adj_total = 0, pairs_total = 0, m_max = 1, bit_total = 0;
     int32_t G = 0, nmax = 0, dmax = -1;
     bool unbounded = false;
     for (int32_t k = 0; k < P; ++k) {
         const bns_dataset *d = ds[k];
-        probs[k] = {d->d_data, d->ld, d->m, d->n, G, adj_total, alpha[k], maxd[k], 0};
+        probs[k] = {d->d_data, d->ld, d->m, d->n, G, adj_total, alpha[k], maxd[k],
+                    (int32_t)std::min<int64_t>(bit_total, INT32_MAX)};
+        bit_total += (int64_t)d->n * ((d->n + 63) / 64);
         for (int32_t v = 0; v < d->n; ++v) var2prob.push_back(k);
         gcards.insert(gcards.end(), d->cards.begin(), d->cards.end());
         G += d->n;
@@ -625,6 +643,8 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     HIP_TRY(dc.adj.ensure((size_t)adj_total));
     HIP_TRY(dc.nbr.ensure(sizeof(int32_t) * (size_t)adj_total));
     HIP_TRY(dc.ipos.ensure(sizeof(int32_t) * (size_t)adj_total));
+    // bit rows are used only by small searches (at most kSmallBitWords words)
+    HIP_TRY(dc.adjbits.ensure(sizeof(uint64_t) * (size_t)std::min<int64_t>(std::max<int64_t>(bit_total, 1), kSmallBitWords)));
     HIP_TRY(dc.rdepth.ensure((size_t)adj_total));
     HIP_TRY(dc.deg.ensure(sizeof(int32_t) * (size_t)G));
     HIP_TRY(dc.rowcnt.ensure(sizeof(int32_t) * (size_t)G));
@@ -655,6 +675,8 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     a.adj = dc.adj.as<uint8_t>();
     a.nbr = dc.nbr.as<int32_t>();
     a.ipos = dc.ipos.as<int32_t>();
+    a.adjbits = dc.adjbits.as<uint64_t>();
+    a.bit_words = bit_total;
     a.deg = dc.deg.as<int32_t>();
     a.rowcnt = dc.rowcnt.as<int32_t>();
     a.rowbase = dc.rowbase.as<int64_t>();
@@ -706,11 +728,18 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     std::vector<bns_depth_stats> stats;
     unsigned long long alive = (unsigned long long)pairs_total;  // edges alive at depth d
     unsigned long long pool_used = 0;
+    const size_t rbytes = ((size_t)adj_total + 7) & ~(size_t)7;
+    bool spec = false;
+    size_t spec_pool = 0;
     int d = 0;
     for (;;) {
         if (!unbounded && d > dmax) break;
         if (d >= kMaxDepths) return fail(BNS_E_TABLE_TOO_LARGE, "the search exceeds %d depths", kMaxDepths);
         int K = per_launch;
+        // Searches on one device tend to repeat: the first launch covers as
+        // many depth sequences as the last search needed (a depth sequence
+        // of a finished search still launches its kernels).
+        if (d == 0 && dc.last_sequences > 0) K = std::min(K, dc.last_sequences);
         if (!unbounded) K = std::min(K, dmax + 1 - d);
         K = std::min(K, kMaxDepths - d);
         // Sepset slots for every edge that may be removed in these depths.
@@ -741,6 +770,18 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
             HIP_TRY(launch_depth_apply(a, s));
         }
         HIP_TRY(hipMemcpyAsync(dc.h_ctl, dc.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        // Results travel in the same round trip when they are small (most
+        // searches finish within one launch): removal depths and a prefix of
+        // the removal records.
+        spec_pool = 0;
+        spec = rbytes + sizeof(int32_t) * kSpecPoolWords <= kSpecBytes;
+        if (spec) {
+            spec_pool = std::min<size_t>(kSpecPoolWords, dc.pool.bytes / sizeof(int32_t));
+            HIP_TRY(dc.results(rbytes + sizeof(int32_t) * spec_pool));
+            HIP_TRY(hipMemcpyAsync(dc.hres, dc.rdepth.p, (size_t)adj_total, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync((char *)dc.hres + rbytes, dc.pool.p, sizeof(int32_t) * spec_pool,
+                                   hipMemcpyDeviceToHost, s));
+        }
         HIP_TRY(hipStreamSynchronize(s));
         const Ctl &c = *dc.h_ctl;
         if (c.error) {
@@ -769,20 +810,26 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
             alive = sd.edges - sd.removed;
         }
         pool_used = c.pool_used;
-        if (c.done) break;
+        if (c.done) {
+            // sequences this search launched up to the one that found no test
+            dc.last_sequences = reached + (small_search(a) ? 0 : 1);
+            break;
+        }
         if (reached != d + K) return fail(BNS_E_INTERNAL, "depth counter %d after launch from %d", reached, d);
         d = reached;
     }
 
     // Results: removal depths (int8 per pair; -1 = kept) and the removal
-    // records of depth >= 1, in one pinned download.
-    const size_t rbytes = ((size_t)adj_total + 7) & ~(size_t)7;
+    // records of depth >= 1, unless the last round trip brought them.
     const size_t pbytes = sizeof(int32_t) * (size_t)pool_used;
-    HIP_TRY(dc.pinned(rbytes + pbytes));
-    char *hres = (char *)dc.hpin;
-    HIP_TRY(hipMemcpyAsync(hres, dc.rdepth.p, (size_t)adj_total, hipMemcpyDeviceToHost, s));
-    if (pool_used) HIP_TRY(hipMemcpyAsync(hres + rbytes, dc.pool.p, pbytes, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    if (!(spec && pool_used <= spec_pool)) {
+        HIP_TRY(dc.results(rbytes + pbytes));
+        HIP_TRY(hipMemcpyAsync(dc.hres, dc.rdepth.p, (size_t)adj_total, hipMemcpyDeviceToHost, s));
+        if (pool_used)
+            HIP_TRY(hipMemcpyAsync((char *)dc.hres + rbytes, dc.pool.p, pbytes, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    const char *hres = (const char *)dc.hres;
     const int8_t *hdep = (const int8_t *)hres;
     const int32_t *hpool = (const int32_t *)(hres + rbytes);
     std::vector<std::unique_ptr<bns_skeleton>> sks((size_t)P);

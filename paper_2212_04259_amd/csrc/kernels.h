@@ -21,6 +21,8 @@ struct DepthArgs {
     uint8_t *adj;             // per problem n*n block at adj_off
     int32_t *nbr;             // frozen adjacency lists, same blocks as adj
     int32_t *ipos;            // ipos[v * n + u] = position of u in the frozen list of v
+    uint64_t *adjbits;        // small searches: adjacency bit rows, ceil(n / 64) words per row
+    int64_t bit_words;        // words of adjbits over all problems
     int32_t *deg;             // per global variable
     int32_t *rowcnt;          // per global variable: alive edges (v, u > v)
     int64_t *rowbase;         // exclusive scan of rowcnt
@@ -49,6 +51,10 @@ struct DepthArgs {
     int32_t grab_fixed;       // tickets per grab (0: from the ticket count)
 };
 
+// Small searches keep the adjacency as bit rows in LDS and prepare each depth
+// inside the removal kernel of the depth before.
+constexpr int kSmallBitWords = 4096;
+__host__ __device__ bool small_search(const DepthArgs &a);
 hipError_t launch_depth_prepare(const DepthArgs &a, hipStream_t s);   // snapshot .. scatter
 hipError_t launch_depth_tests(const DepthArgs &a, int grid, hipStream_t s);
 hipError_t launch_depth_apply(const DepthArgs &a, hipStream_t s);     // removals + finalize

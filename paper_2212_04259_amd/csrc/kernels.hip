@@ -49,6 +49,13 @@ __global__ void k_plain_count(const uint8_t *data, int64_t ld, int64_t m, const 
 // ---------------------------------------------------------------------------
 // Search initialisation: complete graph, no removals, control block reset.
 // ---------------------------------------------------------------------------
+constexpr int kSmallRows = 1024;
+constexpr int64_t kSmallPairs = 65536;
+
+__host__ __device__ bool small_search(const DepthArgs &a) {
+    return a.n_globals <= kSmallRows && a.n_pairs <= kSmallPairs && a.bit_words <= kSmallBitWords;
+}
+
 __global__ void k_init_search(DepthArgs A) {
     const int pi = blockIdx.y;
     const ProbDev P = A.probs[pi];
@@ -58,6 +65,17 @@ __global__ void k_init_search(DepthArgs A) {
         const int64_t i = e / P.n, j = e - i * P.n;
         A.adj[P.adj_off + e] = (i != j) ? 1 : 0;
         A.rdepth[P.adj_off + e] = -1;
+    }
+    if (small_search(A)) {
+        // complete graph as bit rows: bits u < n of row v, except u = v
+        const int W = (P.n + 63) / 64;
+        for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < P.n * W; e += gridDim.x * blockDim.x) {
+            const int v = e / W, w = e - v * W;
+            const int lo = 64 * w, nb = min(64, P.n - lo);
+            uint64_t word = (nb >= 64) ? ~0ull : ((1ull << nb) - 1ull);
+            if (v >= lo && v < lo + 64) word &= ~(1ull << (v - lo));
+            A.adjbits[P.bit_off + e] = word;
+        }
     }
     if (pi == 0 && blockIdx.x == 0) {
         Ctl *c = A.ctl;
@@ -402,10 +420,9 @@ __global__ __launch_bounds__(kWG) void k_scatter(DepthArgs A) {
 // ---------------------------------------------------------------------------
 constexpr int kSmallThreads = 1024;
 constexpr int kSmallWaves = kSmallThreads / 64;
-constexpr int kSmallRows = 1024;
-constexpr int64_t kSmallPairs = 65536;
 
 struct SmallSh {
+    uint64_t bits[kSmallBitWords];  // adjacency bit rows of all problems
     uint64_t bcol[kSmallRows];  // C(x, d) for x <= max degree
     int deg[kSmallRows];
     int rowcnt[kSmallRows];
@@ -436,16 +453,41 @@ BNS_INLINE void small_counts(Ctl *c, const SmallSh &sh, bool depth_ok, int d, in
     }
 }
 
+// Bit u of row v of a problem's adjacency bit rows (W words per row).
+BNS_INLINE bool bit_at(const uint64_t *rows, int W, int v, int u) {
+    return (rows[v * W + (u >> 6)] >> (u & 63)) & 1ull;
+}
+
+// Set bits of row v below u: the position of u in the ascending list of v.
+BNS_INLINE int bits_below(const uint64_t *rows, int W, int v, int u) {
+    const uint64_t *r = rows + v * W;
+    int c = 0;
+    for (int w = 0; w < (u >> 6); ++w) c += __popcll(r[w]);
+    return c + __popcll(r[u >> 6] & ((1ull << (u & 63)) - 1ull));
+}
+
 BNS_INLINE void prepare_block(const DepthArgs &A, Ctl *c, int d, SmallSh &sh) {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int G = A.n_globals;
     for (int i = threadIdx.x; i < kMaxLevels + 2; i += kSmallThreads) sh.hist[i] = 0;
     // frozen adjacency lists, degrees and higher-neighbour counts
+    const uint64_t lt = lanes_below_mask();
     for (int g = w; g < G; g += kSmallWaves) {
-        int dg, hi;
-        snapshot_row(A, g, dg, hi);
+        const ProbDev &P = A.probs[A.var2prob[g]];
+        const int v = g - P.var_off, n = P.n, W = (n + 63) >> 6;
+        const uint64_t *rows = sh.bits + P.bit_off;
+        int32_t *nb = A.nbr + P.adj_off + (int64_t)v * n;
+        int cnt = 0, hi = 0;
+        for (int u0 = 0; u0 < n; u0 += 64) {
+            const int u = u0 + lane;
+            const bool a = (u < n) && bit_at(rows, W, v, u);
+            const uint64_t mask = __ballot(a);
+            if (a) nb[cnt + __popcll(mask & lt)] = u;
+            cnt += __popcll(mask);
+            hi += __popcll(__ballot(a && u > v));
+        }
         if (lane == 0) {
-            sh.deg[g] = dg;
+            sh.deg[g] = cnt;
             sh.rowcnt[g] = hi;
         }
     }
@@ -487,12 +529,12 @@ BNS_INLINE void prepare_block(const DepthArgs &A, Ctl *c, int d, SmallSh &sh) {
     for (int g = w; g < G; g += kSmallWaves) {
         if (sh.rowcnt[g] == 0) continue;
         const ProbDev &P = A.probs[A.var2prob[g]];
-        const int v = g - P.var_off, n = P.n;
+        const int v = g - P.var_off, n = P.n, W = (n + 63) >> 6;
         const bool depth_ok = (P.max_depth < 0 || d <= P.max_depth);
-        const uint8_t *row = A.adj + P.adj_off + (int64_t)v * n;
+        const uint64_t *rows = sh.bits + P.bit_off;
         const int dv = sh.deg[g];
         for (int u = v + 1 + lane; u < n; u += 64) {
-            if (!row[u]) continue;
+            if (!bit_at(rows, W, v, u)) continue;
             uint64_t nA, nB;
             small_counts(c, sh, depth_ok, d, dv, sh.deg[P.var_off + u], nA, nB);
             const uint64_t nt = nA + nB;
@@ -504,19 +546,18 @@ BNS_INLINE void prepare_block(const DepthArgs &A, Ctl *c, int d, SmallSh &sh) {
     __syncthreads();
     if (sh.done) return;
     // pass 2: edge records in level order
-    const uint64_t lt = lanes_below_mask();
     for (int g = w; g < G; g += kSmallWaves) {
         if (sh.rowcnt[g] == 0) continue;
         const int pi = A.var2prob[g];
         const ProbDev &P = A.probs[pi];
-        const int v = g - P.var_off, n = P.n;
+        const int v = g - P.var_off, n = P.n, W = (n + 63) >> 6;
         const bool depth_ok = (P.max_depth < 0 || d <= P.max_depth);
-        const uint8_t *row = A.adj + P.adj_off + (int64_t)v * n;
+        const uint64_t *rows = sh.bits + P.bit_off;
         const int dv = sh.deg[g];
         int cnt = 0;
         for (int u0 = 0; u0 < n; u0 += 64) {
             const int u = u0 + lane;
-            const bool a = (u < n) && row[u];
+            const bool a = (u < n) && bit_at(rows, W, v, u);
             const uint64_t mask = __ballot(a);
             const bool take = a && u > v;
             EdgeRec e;
@@ -529,7 +570,7 @@ BNS_INLINE void prepare_block(const DepthArgs &A, Ctl *c, int d, SmallSh &sh) {
                 e.i = v;
                 e.j = u;
                 e.posj = cnt + __popcll(mask & lt);
-                e.posi = (nB > 0) ? A.ipos[P.adj_off + (int64_t)u * n + v] : 0;
+                e.posi = (nB > 0) ? bits_below(rows, W, u, v) : 0;
                 e.pA = dv - 1;
                 e.pB = du - 1;
                 e.nA = nA;
@@ -562,6 +603,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_prepare_small(DepthArgs A) {
     __shared__ SmallSh sh;
     Ctl *c = A.ctl;
     if (c->done) return;
+    for (int i = threadIdx.x; i < A.bit_words; i += kSmallThreads) sh.bits[i] = A.adjbits[i];
+    __syncthreads();
     prepare_block(A, c, c->depth, sh);
 }
 
@@ -914,7 +957,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
 // [problem, i, j, s_1 .. s_d] (d + 3 words), one atomic per wave.
 BNS_INLINE void apply_edges(const DepthArgs &A, Ctl *c, int d, unsigned long long first,
                             unsigned long long stride, unsigned long long &req,
-                            unsigned long long &rem) {
+                            unsigned long long &rem, uint64_t *lds_bits = nullptr) {
     const unsigned long long E = c->n_edges;
     const int lane = threadIdx.x & 63;
     const uint64_t lt = lanes_below_mask();
@@ -961,8 +1004,15 @@ BNS_INLINE void apply_edges(const DepthArgs &A, Ctl *c, int d, unsigned long lon
         }
         const int64_t ij = P.adj_off + (int64_t)r.i * n + r.j;
         const int64_t ji = P.adj_off + (int64_t)r.j * n + r.i;
-        A.adj[ij] = 0;
-        A.adj[ji] = 0;
+        if (lds_bits) {
+            const int W = (n + 63) >> 6;
+            uint64_t *rows = lds_bits + P.bit_off;
+            atomicAnd(&rows[r.i * W + (r.j >> 6)], ~(1ull << (r.j & 63)));
+            atomicAnd(&rows[r.j * W + (r.i >> 6)], ~(1ull << (r.i & 63)));
+        } else {
+            A.adj[ij] = 0;
+            A.adj[ji] = 0;
+        }
         A.rdepth[ij] = (int8_t)d;
         A.rdepth[ji] = (int8_t)d;
     }
@@ -1014,8 +1064,11 @@ __global__ __launch_bounds__(kSmallThreads) void k_apply_small(DepthArgs A) {
     if (c->done) return;
     const int d = c->depth;
     const int w = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < A.bit_words; i += kSmallThreads) sh.bits[i] = A.adjbits[i];
+    __syncthreads();
     unsigned long long req = 0, rem = 0;
-    apply_edges(A, c, d, (unsigned long long)w * 64, (unsigned long long)kSmallThreads, req, rem);
+    apply_edges(A, c, d, (unsigned long long)w * 64, (unsigned long long)kSmallThreads, req, rem,
+                sh.bits);
     req = wave_sum(req);
     rem = wave_sum(rem);
     if ((threadIdx.x & 63) == 0) {
@@ -1036,6 +1089,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_apply_small(DepthArgs A) {
         c->depth = d + 1;
     }
     __syncthreads();
+    // the bit rows after the removals, for the next depth's removal kernel
+    for (int i = threadIdx.x; i < A.bit_words; i += kSmallThreads) A.adjbits[i] = sh.bits[i];
     prepare_block(A, c, d + 1, sh);
 }
 
@@ -1044,9 +1099,6 @@ __global__ __launch_bounds__(kSmallThreads) void k_apply_small(DepthArgs A) {
 // ---------------------------------------------------------------------------
 static int grid_rows(int n_globals) { return (n_globals + kWaves - 1) / kWaves; }
 
-static bool small_search(const DepthArgs &a) {
-    return a.n_globals <= kSmallRows && a.n_pairs <= kSmallPairs;
-}
 
 // Small searches prepare depth 0 here and every later depth in the removal
 // kernel of the depth before; larger ones prepare each depth in
