@@ -22,18 +22,33 @@ __device__ inline uint64_t lanes_below_mask() {
 
 // Position of rank rr among the size-d subsets of {0..p-1} in lexicographic
 // order (one thread, sequential): writes c[0..d).
-__device__ inline void unrank_serial(const uint64_t *B, int rows, int64_t p, int d, uint64_t rr,
-                                     int32_t *c) {
+// A view of the binomial table: C(n, k) at tab[n * stride + k] for n < rows
+// (the full table in device memory, or a slice n < rows, k < stride staged
+// in LDS); saturated beyond it.
+struct Binom {
+    const uint64_t *tab;
+    int stride;
+    int rows;
+    __device__ uint64_t at(int64_t n, int k) const {
+        if (n < 0 || k < 0 || k > n) return 0;
+        if (n >= rows || k >= stride) return ~0ull >> 2;
+        return tab[n * stride + k];
+    }
+};
+
+// Serial lexicographic unranking (one lane): positions of the rank-rr size-d
+// subset of {0..p-1}.
+__device__ inline void unrank_serial(const Binom &B, int64_t p, int d, uint64_t rr, int32_t *c) {
     int64_t x0 = 0;
     for (int k = 0; k < d; ++k) {
         const int j = d - k - 1;
-        const uint64_t base = binom_at(B, rows, p - x0, j + 1);
+        const uint64_t base = B.at(p - x0, j + 1);
         int64_t x = x0;
         // S(x) = number of subsets (with the current prefix) whose k-th element is < x
         //      = C(p - x0, j + 1) - C(p - x, j + 1)   (hockey-stick identity)
-        while (x + 1 <= p - j - 1 && base - binom_at(B, rows, p - (x + 1), j + 1) <= rr) ++x;
+        while (x + 1 <= p - j - 1 && base - B.at(p - (x + 1), j + 1) <= rr) ++x;
         c[k] = (int32_t)x;
-        rr -= base - binom_at(B, rows, p - x, j + 1);
+        rr -= base - B.at(p - x, j + 1);
         x0 = x + 1;
     }
 }
@@ -421,8 +436,13 @@ __global__ __launch_bounds__(kWG) void k_scatter(DepthArgs A) {
 constexpr int kSmallThreads = 1024;
 constexpr int kSmallWaves = kSmallThreads / 64;
 
+constexpr int kSmallProbs = 8;      // problem records staged in LDS
+constexpr int kApplyBinom = 1024;   // binomials C(n, k <= d) staged for the removal records
+
 struct SmallSh {
     uint64_t bits[kSmallBitWords];  // adjacency bit rows of all problems
+    uint64_t btab[kApplyBinom];
+    ProbDev probs[kSmallProbs];
     uint64_t bcol[kSmallRows];  // C(x, d) for x <= max degree
     int deg[kSmallRows];
     int rowcnt[kSmallRows];
@@ -453,6 +473,24 @@ BNS_INLINE void small_counts(Ctl *c, const SmallSh &sh, bool depth_ok, int d, in
     }
 }
 
+// Problem of global variable g: from the LDS copies when there are few problems.
+BNS_INLINE int small_prob_index(const DepthArgs &A, const SmallSh &sh, int g) {
+    if (A.n_probs > kSmallProbs) return A.var2prob[g];
+    int pi = 0;
+    for (int k = 1; k < A.n_probs; ++k)
+        if (sh.probs[k].var_off <= g) pi = k;
+    return pi;
+}
+BNS_INLINE const ProbDev &small_prob(const DepthArgs &A, const SmallSh &sh, int pi) {
+    return A.n_probs > kSmallProbs ? A.probs[pi] : sh.probs[pi];
+}
+
+// Stages the bit rows and problem records of a small search in LDS.
+BNS_INLINE void small_load(const DepthArgs &A, SmallSh &sh) {
+    for (int i = threadIdx.x; i < A.bit_words; i += kSmallThreads) sh.bits[i] = A.adjbits[i];
+    if (A.n_probs <= kSmallProbs && threadIdx.x < (unsigned)A.n_probs) sh.probs[threadIdx.x] = A.probs[threadIdx.x];
+}
+
 // Bit u of row v of a problem's adjacency bit rows (W words per row).
 BNS_INLINE bool bit_at(const uint64_t *rows, int W, int v, int u) {
     return (rows[v * W + (u >> 6)] >> (u & 63)) & 1ull;
@@ -466,33 +504,86 @@ BNS_INLINE int bits_below(const uint64_t *rows, int W, int v, int u) {
     return c + __popcll(r[u >> 6] & ((1ull << (u & 63)) - 1ull));
 }
 
+// Item i of the bit rows (one 64-bit word of one row): problem, row, word.
+struct BitItem {
+    int pi, v, w, W;
+};
+BNS_INLINE BitItem bit_item(const DepthArgs &A, const SmallSh &sh, int i) {
+    int pi = 0;
+    if (A.n_probs <= kSmallProbs) {
+        for (int k = 1; k < A.n_probs; ++k)
+            if (sh.probs[k].bit_off <= i) pi = k;
+    } else {
+        int lo = 0, hi = A.n_probs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (A.probs[mid].bit_off <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        pi = lo;
+    }
+    const ProbDev &P = small_prob(A, sh, pi);
+    const int W = (P.n + 63) >> 6;
+    const int r = i - P.bit_off;
+    const int v = r / W;
+    return BitItem{pi, v, r - v * W, W};
+}
+
+// Bits of word w (bits 64w .. 64w + 63) above index v.
+BNS_INLINE uint64_t bits_above(uint64_t x, int w, int v) {
+    const int lo = 64 * w;
+    if (v < lo) return x;
+    if (v >= lo + 63) return 0ull;
+    return x & (~0ull << (v - lo + 1));
+}
+
+// Preparation of depth d by one workgroup from the bit rows in LDS.  Work is
+// spread one thread per variable (degrees) or per slice of a row word
+// (lists, levels, records): each word is cut into L slices of 64 / L bits,
+// L a power of two chosen so that the slices about fill the workgroup.
 BNS_INLINE void prepare_block(const DepthArgs &A, Ctl *c, int d, SmallSh &sh) {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int G = A.n_globals;
+    const int NW = (int)A.bit_words;
+    int lgL = 0;
+    while (lgL < 6 && (NW << (lgL + 1)) <= kSmallThreads) ++lgL;
+    const int NS = NW << lgL;            // slices
+    const int sbits = 64 >> lgL;         // bits per slice
+    const uint64_t smask = (sbits == 64) ? ~0ull : ((1ull << sbits) - 1ull);
     for (int i = threadIdx.x; i < kMaxLevels + 2; i += kSmallThreads) sh.hist[i] = 0;
-    // frozen adjacency lists, degrees and higher-neighbour counts
-    const uint64_t lt = lanes_below_mask();
-    for (int g = w; g < G; g += kSmallWaves) {
-        const ProbDev &P = A.probs[A.var2prob[g]];
-        const int v = g - P.var_off, n = P.n, W = (n + 63) >> 6;
-        const uint64_t *rows = sh.bits + P.bit_off;
-        int32_t *nb = A.nbr + P.adj_off + (int64_t)v * n;
+    // degrees and higher-neighbour counts, one thread per variable
+    for (int g = threadIdx.x; g < G; g += kSmallThreads) {
+        const ProbDev &P = small_prob(A, sh, small_prob_index(A, sh, g));
+        const int v = g - P.var_off, W = (P.n + 63) >> 6;
+        const uint64_t *row = sh.bits + P.bit_off + v * W;
         int cnt = 0, hi = 0;
-        for (int u0 = 0; u0 < n; u0 += 64) {
-            const int u = u0 + lane;
-            const bool a = (u < n) && bit_at(rows, W, v, u);
-            const uint64_t mask = __ballot(a);
-            if (a) nb[cnt + __popcll(mask & lt)] = u;
-            cnt += __popcll(mask);
-            hi += __popcll(__ballot(a && u > v));
+        for (int k = 0; k < W; ++k) {
+            const uint64_t x = row[k];
+            cnt += __popcll(x);
+            hi += __popcll(bits_above(x, k, v));
         }
-        if (lane == 0) {
-            sh.deg[g] = cnt;
-            sh.rowcnt[g] = hi;
-        }
+        sh.deg[g] = cnt;
+        sh.rowcnt[g] = hi;
     }
     __syncthreads();
-    // edge total and largest degree
+    // frozen adjacency lists (ascending), one thread per row word; edge total
+    // and largest degree
+    for (int i = threadIdx.x; i < NS; i += kSmallThreads) {
+        const BitItem it = bit_item(A, sh, i >> lgL);
+        const int s0 = (i & ((1 << lgL) - 1)) * sbits;  // first bit of the slice
+        const ProbDev &P = small_prob(A, sh, it.pi);
+        const uint64_t *row = sh.bits + P.bit_off + it.v * it.W;
+        int pos = 0;
+        for (int k = 0; k < it.w; ++k) pos += __popcll(row[k]);
+        const uint64_t word = row[it.w];
+        if (s0) pos += __popcll(word & ((1ull << s0) - 1ull));
+        int32_t *nb = A.nbr + P.adj_off + (int64_t)it.v * P.n;
+        uint64_t x = word & (smask << s0);
+        while (x) {
+            nb[pos++] = 64 * it.w + __ffsll((long long)x) - 1;
+            x &= x - 1ull;
+        }
+    }
     {
         int64_t s = 0;
         int md = 0;
@@ -525,16 +616,17 @@ BNS_INLINE void prepare_block(const DepthArgs &A, Ctl *c, int d, SmallSh &sh) {
         if (d >= kMaxDepths) c->error = kDevDepthTooLarge;
     }
     __syncthreads();
-    // pass 1: level histogram
-    for (int g = w; g < G; g += kSmallWaves) {
-        if (sh.rowcnt[g] == 0) continue;
-        const ProbDev &P = A.probs[A.var2prob[g]];
-        const int v = g - P.var_off, n = P.n, W = (n + 63) >> 6;
+    // pass 1: level histogram, one thread per row word
+    for (int i = threadIdx.x; i < NS; i += kSmallThreads) {
+        const BitItem it = bit_item(A, sh, i >> lgL);
+        const int s0 = (i & ((1 << lgL) - 1)) * sbits;
+        const ProbDev &P = small_prob(A, sh, it.pi);
         const bool depth_ok = (P.max_depth < 0 || d <= P.max_depth);
-        const uint64_t *rows = sh.bits + P.bit_off;
-        const int dv = sh.deg[g];
-        for (int u = v + 1 + lane; u < n; u += 64) {
-            if (!bit_at(rows, W, v, u)) continue;
+        const int dv = sh.deg[P.var_off + it.v];
+        uint64_t x = bits_above(sh.bits[P.bit_off + it.v * it.W + it.w], it.w, it.v) & (smask << s0);
+        while (x) {
+            const int u = 64 * it.w + __ffsll((long long)x) - 1;
+            x &= x - 1ull;
             uint64_t nA, nB;
             small_counts(c, sh, depth_ok, d, dv, sh.deg[P.var_off + u], nA, nB);
             const uint64_t nt = nA + nB;
@@ -545,56 +637,43 @@ BNS_INLINE void prepare_block(const DepthArgs &A, Ctl *c, int d, SmallSh &sh) {
     if (w == 0) levels_wave(A, c, sh.hist, d, sh.cursor, &sh.done);
     __syncthreads();
     if (sh.done) return;
-    // pass 2: edge records in level order
-    for (int g = w; g < G; g += kSmallWaves) {
-        if (sh.rowcnt[g] == 0) continue;
-        const int pi = A.var2prob[g];
-        const ProbDev &P = A.probs[pi];
-        const int v = g - P.var_off, n = P.n, W = (n + 63) >> 6;
+    // pass 2: edge records in level order, one thread per row word
+    for (int i = threadIdx.x; i < NS; i += kSmallThreads) {
+        const BitItem it = bit_item(A, sh, i >> lgL);
+        const int s0 = (i & ((1 << lgL) - 1)) * sbits;
+        const ProbDev &P = small_prob(A, sh, it.pi);
         const bool depth_ok = (P.max_depth < 0 || d <= P.max_depth);
         const uint64_t *rows = sh.bits + P.bit_off;
-        const int dv = sh.deg[g];
-        int cnt = 0;
-        for (int u0 = 0; u0 < n; u0 += 64) {
-            const int u = u0 + lane;
-            const bool a = (u < n) && bit_at(rows, W, v, u);
-            const uint64_t mask = __ballot(a);
-            const bool take = a && u > v;
+        const uint64_t *row = rows + it.v * it.W;
+        const int dv = sh.deg[P.var_off + it.v];
+        int pos = 0;  // position of the next neighbour in the list of v
+        for (int k = 0; k < it.w; ++k) pos += __popcll(row[k]);
+        const uint64_t word = row[it.w];
+        if (s0) pos += __popcll(word & ((1ull << s0) - 1ull));  // neighbours before the slice
+        const uint64_t sl = word & (smask << s0);
+        const uint64_t above = bits_above(sl, it.w, it.v);
+        pos += __popcll(sl & ~above);  // neighbours of the slice below v come first
+        uint64_t x = above;
+        while (x) {
+            const int u = 64 * it.w + __ffsll((long long)x) - 1;
+            x &= x - 1ull;
+            const int du = sh.deg[P.var_off + u];
+            uint64_t nA, nB;
+            small_counts(c, sh, depth_ok, d, dv, du, nA, nB);
             EdgeRec e;
-            int lv = -1;
-            if (take) {
-                const int du = sh.deg[P.var_off + u];
-                uint64_t nA, nB;
-                small_counts(c, sh, depth_ok, d, dv, du, nA, nB);
-                e.prob = pi;
-                e.i = v;
-                e.j = u;
-                e.posj = cnt + __popcll(mask & lt);
-                e.posi = (nB > 0) ? bits_below(rows, W, u, v) : 0;
-                e.pA = dv - 1;
-                e.pB = du - 1;
-                e.nA = nA;
-                e.n = nA + nB;
-                e.levels = e.n ? 64 - __clzll(e.n) : 0;
-                lv = e.levels;
-            }
-            cnt += __popcll(mask);
-            uint64_t todo = __ballot(take);
-            unsigned int pos = 0;
-            while (todo) {
-                const int leader = __ffsll((long long)todo) - 1;
-                const int L = __shfl(lv, leader, 64);
-                const uint64_t same = __ballot(take && lv == L);
-                unsigned int b = 0;
-                if (lane == leader) b = atomicAdd(&sh.cursor[L], (unsigned int)__popcll(same));
-                b = __shfl(b, leader, 64);
-                if (take && lv == L) pos = b + (unsigned int)__popcll(same & lt);
-                todo &= ~same;
-            }
-            if (take) {
-                A.edges[pos] = e;
-                A.min_accept[pos] = ~0ull;
-            }
+            e.prob = it.pi;
+            e.i = it.v;
+            e.j = u;
+            e.posj = pos++;
+            e.posi = (nB > 0) ? bits_below(rows, it.W, u, it.v) : 0;
+            e.pA = dv - 1;
+            e.pB = du - 1;
+            e.nA = nA;
+            e.n = nA + nB;
+            e.levels = e.n ? 64 - __clzll(e.n) : 0;
+            const unsigned int slot = atomicAdd(&sh.cursor[e.levels], 1u);
+            A.edges[slot] = e;
+            A.min_accept[slot] = ~0ull;
         }
     }
 }
@@ -603,7 +682,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_prepare_small(DepthArgs A) {
     __shared__ SmallSh sh;
     Ctl *c = A.ctl;
     if (c->done) return;
-    for (int i = threadIdx.x; i < A.bit_words; i += kSmallThreads) sh.bits[i] = A.adjbits[i];
+    small_load(A, sh);
     __syncthreads();
     prepare_block(A, c, c->depth, sh);
 }
@@ -955,67 +1034,98 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
 // leave the graph; the canonical test count and removals are tallied into
 // req and rem.  Removal records of depth >= 1 go to the pool, densely:
 // [problem, i, j, s_1 .. s_d] (d + 3 words), one atomic per wave.
-BNS_INLINE void apply_edges(const DepthArgs &A, Ctl *c, int d, unsigned long long first,
-                            unsigned long long stride, unsigned long long &req,
-                            unsigned long long &rem, uint64_t *lds_bits = nullptr) {
-    const unsigned long long E = c->n_edges;
+// One edge per lane (all lanes of the wave call it together; valid marks
+// the lanes that hold an edge).
+BNS_INLINE void apply_one(const DepthArgs &A, Ctl *c, int d, bool valid, const EdgeRec &r,
+                          unsigned long long ma, unsigned long long &rem, const Binom &bn,
+                          const ProbDev *probs, uint64_t *lds_bits) {
     const int lane = threadIdx.x & 63;
     const uint64_t lt = lanes_below_mask();
-    for (unsigned long long base = first; base < E; base += stride) {
-        const unsigned long long e = base + lane;
-        const bool valid = e < E;
-        EdgeRec r;
-        unsigned long long ma = ~0ull;
-        if (valid) {
-            r = A.edges[e];
-            ma = A.min_accept[e];
-            req += (ma == ~0ull) ? r.n : ma + 1;
-        }
-        const bool removed = valid && ma != ~0ull;
-        const uint64_t rmask = __ballot(removed);
-        if (rmask == 0ull) continue;
-        rem += removed ? 1 : 0;
-        unsigned long long off = 0;
-        if (d > 0) {
-            const unsigned long long rec = (unsigned long long)(d + 3);
-            unsigned long long b0 = 0;
-            if (lane == 0) b0 = atomicAdd(&c->pool_used, rec * (unsigned long long)__popcll(rmask));
-            b0 = __shfl(b0, 0, 64);
-            off = b0 + rec * (unsigned long long)__popcll(rmask & lt);
-        }
-        if (!removed) continue;
-        const ProbDev &P = A.probs[r.prob];
-        const int n = P.n;
-        if (d > 0) {
-            int32_t cpos[kMaxZ];
-            const bool sideA = ma < r.nA;
-            const int owner = sideA ? r.i : r.j;
-            const int skip = sideA ? r.posj : r.posi;
-            const int64_t p = sideA ? r.pA : r.pB;
-            unrank_serial(A.binom, A.binom_rows, p, d, sideA ? ma : ma - r.nA, cpos);
-            const int32_t *nbo = A.nbr + P.adj_off + (int64_t)owner * n;
-            A.pool[off] = r.prob;
-            A.pool[off + 1] = r.i;
-            A.pool[off + 2] = r.j;
-            for (int k = 0; k < d; ++k) {
-                const int q = cpos[k];
-                A.pool[off + 3 + k] = nbo[q + (q >= skip ? 1 : 0)];
-            }
-        }
-        const int64_t ij = P.adj_off + (int64_t)r.i * n + r.j;
-        const int64_t ji = P.adj_off + (int64_t)r.j * n + r.i;
-        if (lds_bits) {
-            const int W = (n + 63) >> 6;
-            uint64_t *rows = lds_bits + P.bit_off;
-            atomicAnd(&rows[r.i * W + (r.j >> 6)], ~(1ull << (r.j & 63)));
-            atomicAnd(&rows[r.j * W + (r.i >> 6)], ~(1ull << (r.i & 63)));
-        } else {
-            A.adj[ij] = 0;
-            A.adj[ji] = 0;
-        }
-        A.rdepth[ij] = (int8_t)d;
-        A.rdepth[ji] = (int8_t)d;
+    const bool removed = valid && ma != ~0ull;
+    const uint64_t rmask = __ballot(removed);
+    if (rmask == 0ull) return;
+    rem += removed ? 1 : 0;
+    unsigned long long off = 0;
+    if (d > 0) {
+        const unsigned long long rec = (unsigned long long)(d + 3);
+        unsigned long long b0 = 0;
+        if (lane == 0) b0 = atomicAdd(&c->pool_used, rec * (unsigned long long)__popcll(rmask));
+        b0 = __shfl(b0, 0, 64);
+        off = b0 + rec * (unsigned long long)__popcll(rmask & lt);
     }
+    if (!removed) return;
+    const ProbDev &P = probs[r.prob];
+    const int n = P.n;
+    if (d > 0) {
+        int32_t cpos[kMaxZ];
+        const bool sideA = ma < r.nA;
+        const int owner = sideA ? r.i : r.j;
+        const int skip = sideA ? r.posj : r.posi;
+        const int64_t p = sideA ? r.pA : r.pB;
+        unrank_serial(bn, p, d, sideA ? ma : ma - r.nA, cpos);
+        const int32_t *nbo = A.nbr + P.adj_off + (int64_t)owner * n;
+        A.pool[off] = r.prob;
+        A.pool[off + 1] = r.i;
+        A.pool[off + 2] = r.j;
+        for (int k = 0; k < d; ++k) {
+            const int q = cpos[k];
+            A.pool[off + 3 + k] = nbo[q + (q >= skip ? 1 : 0)];
+        }
+    }
+    const int64_t ij = P.adj_off + (int64_t)r.i * n + r.j;
+    const int64_t ji = P.adj_off + (int64_t)r.j * n + r.i;
+    if (lds_bits) {
+        const int W = (n + 63) >> 6;
+        uint64_t *rows = lds_bits + P.bit_off;
+        atomicAnd(&rows[r.i * W + (r.j >> 6)], ~(1ull << (r.j & 63)));
+        atomicAnd(&rows[r.j * W + (r.i >> 6)], ~(1ull << (r.i & 63)));
+    } else {
+        A.adj[ij] = 0;
+        A.adj[ji] = 0;
+    }
+    A.rdepth[ij] = (int8_t)d;
+    A.rdepth[ji] = (int8_t)d;
+}
+
+BNS_INLINE void apply_edges(const DepthArgs &A, Ctl *c, int d, unsigned long long first,
+                            unsigned long long stride, unsigned long long &req,
+                            unsigned long long &rem, const Binom &bn, const ProbDev *probs,
+                            uint64_t *lds_bits = nullptr) {
+    const unsigned long long E = c->n_edges;
+    const int lane = threadIdx.x & 63;
+    // two strides per trip: both edges' loads are in flight together
+    for (unsigned long long base = first; base < E; base += 2 * stride) {
+        const unsigned long long e0 = base + lane, e1 = base + stride + lane;
+        const bool v0 = e0 < E, v1 = e1 < E;
+        EdgeRec r0, r1;
+        unsigned long long ma0 = ~0ull, ma1 = ~0ull;
+        if (v0) {
+            r0 = A.edges[e0];
+            ma0 = A.min_accept[e0];
+        }
+        if (v1) {
+            r1 = A.edges[e1];
+            ma1 = A.min_accept[e1];
+        }
+        if (v0) req += (ma0 == ~0ull) ? r0.n : ma0 + 1;
+        if (v1) req += (ma1 == ~0ull) ? r1.n : ma1 + 1;
+        apply_one(A, c, d, v0, r0, ma0, rem, bn, probs, lds_bits);
+        if (base + stride < E) apply_one(A, c, d, v1, r1, ma1, rem, bn, probs, lds_bits);
+    }
+}
+
+// Binomials C(n, k), n <= max degree, k <= d, staged in LDS (the unranking
+// of a separating set walks them serially); the device table otherwise.
+BNS_INLINE Binom stage_binom(const DepthArgs &A, int maxdeg, int d, uint64_t *lds, int cap,
+                             int nthreads) {
+    const int rows = maxdeg + 1, stride = d + 1;
+    if (d > kMaxZ || rows > A.binom_rows || rows * stride > cap)
+        return Binom{A.binom, kBinomK, A.binom_rows};
+    for (int i = threadIdx.x; i < rows * stride; i += nthreads) {
+        const int n = i / stride, k = i - n * stride;
+        lds[i] = A.binom[n * kBinomK + k];
+    }
+    return Binom{lds, stride, rows};
 }
 
 // Depth completion over many workgroups; the last one to finish advances
@@ -1024,10 +1134,13 @@ __global__ __launch_bounds__(kWG) void k_apply(DepthArgs A) {
     Ctl *c = A.ctl;
     if (c->done) return;
     __shared__ unsigned long long red[2][kWaves];
+    __shared__ uint64_t btab[kApplyBinom];
     const int d = c->depth;
+    const Binom bn = stage_binom(A, c->maxdeg, d, btab, kApplyBinom, kWG);
+    __syncthreads();
     unsigned long long req = 0, rem = 0;
     apply_edges(A, c, d, (unsigned long long)blockIdx.x * kWG + (threadIdx.x & ~63u),
-                (unsigned long long)gridDim.x * kWG, req, rem);
+                (unsigned long long)gridDim.x * kWG, req, rem, bn, A.probs);
     req = wave_sum(req);
     rem = wave_sum(rem);
     if ((threadIdx.x & 63) == 0) {
@@ -1064,11 +1177,12 @@ __global__ __launch_bounds__(kSmallThreads) void k_apply_small(DepthArgs A) {
     if (c->done) return;
     const int d = c->depth;
     const int w = threadIdx.x >> 6;
-    for (int i = threadIdx.x; i < A.bit_words; i += kSmallThreads) sh.bits[i] = A.adjbits[i];
+    small_load(A, sh);
+    const Binom bn = stage_binom(A, c->maxdeg, d, sh.btab, kApplyBinom, kSmallThreads);
     __syncthreads();
     unsigned long long req = 0, rem = 0;
     apply_edges(A, c, d, (unsigned long long)w * 64, (unsigned long long)kSmallThreads, req, rem,
-                sh.bits);
+                bn, A.n_probs <= kSmallProbs ? sh.probs : A.probs, sh.bits);
     req = wave_sum(req);
     rem = wave_sum(rem);
     if ((threadIdx.x & 63) == 0) {
