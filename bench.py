@@ -48,6 +48,36 @@ def cpu_baseline(datasets, budget_s=10.0):
                 sample=f"{runs} full run(s) of the workload, single thread, {el:.1f} s")
 
 
+def precision_report(bns, handle, ds, per_depth=2000, seed=7):
+    """FP32 G^2 (the default arithmetic) against FP64 on a seeded sample of
+    tests of the workload: random (x, y, Z) with |Z| = 0..3 over its variables.
+    The relative error covers the results the FP32 form reports without an
+    FP64 re-check (recheck band 0, so only the propagated-bound re-checks
+    remain); decisions are compared for every test."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    tests = []
+    for d in range(4):
+        for _ in range(per_depth):
+            vs = rng.choice(ds.n_vars, size=d + 2, replace=False)
+            tests.append((int(vs[0]), int(vs[1]), tuple(int(v) for v in vs[2:])))
+    r32 = bns.bns_ci_batch(handle, tests, ds.alpha,
+                           bns.bns_options_default(precision=0, recheck_band=0.0))
+    r64 = bns.bns_ci_batch(handle, tests, ds.alpha, bns.bns_options_default(precision=1))
+    raw = (r32["flags"] & 2) == 0
+    rel = np.abs(r32["g2"] - r64["g2"]) / np.maximum(np.abs(r64["g2"]), 1.0)
+    rr = rel[raw]
+    return {
+        "tests": len(tests),
+        "conditioning_sizes": [0, 1, 2, 3],
+        "g2_rel_err_max": float(rr.max()) if rr.size else 0.0,
+        "g2_rel_err_p99": float(np.quantile(rr, 0.99)) if rr.size else 0.0,
+        "g2_rel_err_median": float(np.median(rr)) if rr.size else 0.0,
+        "rechecked_fraction": float(1.0 - raw.mean()),
+        "decisions_equal_fp64": bool(np.array_equal(r32["flags"] & 1, r64["flags"] & 1)),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +93,9 @@ def main():
     ap.add_argument("--test-group", type=int, default=0, help="0 auto, 1 wave, 2 workgroup")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the given options instead of the autotuned ones")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (profiler byte calibration)")
     a = ap.parse_args()
@@ -99,6 +132,13 @@ def main():
                  split_min_samples=a.split_min, units_per_group=a.units_per_group,
                  test_group=a.test_group)
     opt = bns.bns_options_default(**knobs)
+    tuned = None
+    if not a.no_autotune:
+        # launch options chosen by the library's autotuner (untimed setup)
+        opt = bns.bns_autotune(handles, alphas, maxd, opt)
+        tuned = {f: getattr(opt, f) for f in ("test_group", "max_replicas", "lds_bytes",
+                                               "tickets_per_grab")}
+        knobs.update(tuned)
 
     def step(o):
         if len(handles) == 1:
@@ -155,6 +195,7 @@ def main():
             "max_depth": maxd[0],
             "g2_arithmetic": "fp64" if a.precision == 1 else "fp32 + fp64 recheck",
             "form": "batched persistent per-depth launch",
+            "autotuned": tuned,
         },
         "tests_required_per_step": required,
         "tests_executed_per_step": executed,
@@ -189,6 +230,8 @@ def main():
                              "same_skeleton_and_sepsets": bool(same)}
         out["speedup_vs_plain"] = out["value"] / out["plain_form"]["value"]
 
+    if not a.no_precision:
+        out["precision_fp32_vs_fp64"] = precision_report(bns, handles[0], dss[0])
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(dss)
     print(json.dumps(out), flush=True)

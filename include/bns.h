@@ -200,6 +200,18 @@ bns_status bns_pc_skeleton_batch(const bns_dataset *const *ds, int32_t n_problem
                                  const double *alpha, const int32_t *max_depth,
                                  const bns_options *opt, bns_skeleton **outs);
 
+/* Chooses launch options for the batched search of these datasets (the tile
+ * shape of the per-depth test kernel: lanes per test, LDS budget and table
+ * replication, tests per grab) by timing complete trial searches, one option
+ * at a time from the defaults, each candidate measured `trials` times
+ * (median; 0 = 3).  *best receives base with the fastest choices filled in
+ * (base NULL = defaults).  The choice is cached per device and workload
+ * (problem sizes, alphas, max depths), so repeated calls return at once.
+ * The trial searches run on the device like bns_pc_skeleton_batch. */
+bns_status bns_autotune(const bns_dataset *const *ds, int32_t n_problems, const double *alpha,
+                        const int32_t *max_depth, const bns_options *base, int32_t trials,
+                        bns_options *best);
+
 int32_t bns_skeleton_n_vars(const bns_skeleton *sk);
 
 /* adj: n_vars * n_vars uint8, adj[i * n + j] = 1 iff edge i - j survived. */

@@ -15,6 +15,7 @@ from ._lib import (  # noqa: F401
     BNS_PREC_FP64,
     EXPORTS,
     BnsError,
+    bns_autotune,
     Dataset,
     Skeleton,
     bns_ci_batch,

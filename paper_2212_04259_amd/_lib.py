@@ -31,6 +31,7 @@ EXPORTS = [
     "bns_dataset_free", "bns_ci_batch", "bns_pc_skeleton", "bns_pc_skeleton_dataset",
     "bns_pc_skeleton_batch", "bns_skeleton_n_vars", "bns_skeleton_adjacency",
     "bns_skeleton_sepset", "bns_skeleton_removals", "bns_skeleton_stats", "bns_skeleton_free",
+    "bns_autotune",
 ]
 
 
@@ -102,6 +103,8 @@ def load():
     L.bns_pc_skeleton_dataset.argtypes = [vp, dbl, i32, P(bns_options), P(vp)]
     L.bns_pc_skeleton_batch.restype = i32
     L.bns_pc_skeleton_batch.argtypes = [vp, i32, vp, vp, P(bns_options), vp]
+    L.bns_autotune.restype = i32
+    L.bns_autotune.argtypes = [vp, i32, vp, vp, P(bns_options), i32, P(bns_options)]
     L.bns_skeleton_n_vars.restype = i32
     L.bns_skeleton_n_vars.argtypes = [vp]
     L.bns_skeleton_adjacency.restype = i32
@@ -262,6 +265,21 @@ def bns_pc_skeleton_dataset(ds: Dataset, alpha: float = 0.05, max_depth: int = -
     _check(load().bns_pc_skeleton_dataset(ds.handle, float(alpha), int(max_depth),
                                           ctypes.byref(o), ctypes.byref(h)))
     return _collect(h)
+
+
+def bns_autotune(datasets, alphas, max_depths, base: bns_options | None = None,
+                 trials: int = 0) -> bns_options:
+    """Launch options for the batched search of these datasets, chosen by
+    timing trial searches in the library (cached per device and workload)."""
+    k = len(datasets)
+    hs = (ctypes.c_void_p * k)(*[d.handle for d in datasets])
+    al = np.ascontiguousarray(alphas, dtype=np.float64)
+    md = np.ascontiguousarray(max_depths, dtype=np.int32)
+    b = base if base is not None else bns_options_default()
+    out = bns_options()
+    _check(load().bns_autotune(ctypes.cast(hs, ctypes.c_void_p), k, _ptr(al), _ptr(md),
+                               ctypes.byref(b), int(trials), ctypes.byref(out)))
+    return out
 
 
 def bns_pc_skeleton_batch(datasets, alphas, max_depths, options: bns_options | None = None):

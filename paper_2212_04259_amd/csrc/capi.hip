@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -1041,6 +1042,95 @@ extern "C" bns_status bns_pc_skeleton_batch(const bns_dataset *const *ds, int32_
         return st;
     }
     for (int32_t k = 0; k < n_problems; ++k) outs[k] = res[k];
+    return BNS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuning of the batched search's launch options
+// ---------------------------------------------------------------------------
+struct TuneEntry {
+    int device;
+    std::vector<int64_t> key;
+    bns_options best;
+};
+static std::mutex g_tune_mu;
+static std::vector<TuneEntry> g_tune;
+
+extern "C" bns_status bns_autotune(const bns_dataset *const *ds, int32_t n_problems,
+                                   const double *alpha, const int32_t *max_depth,
+                                   const bns_options *base, int32_t trials, bns_options *best) {
+    if (!ds || !alpha || !max_depth || !best || n_problems < 1)
+        return fail(BNS_E_INVALID_ARG, "NULL argument or n_problems < 1");
+    if (trials < 0 || trials > 100) return fail(BNS_E_INVALID_ARG, "trials must be in [0, 100]");
+    bns_options o;
+    bns_status st = read_options(base, &o);
+    if (st != BNS_OK) return st;
+    if (o.form != BNS_FORM_BATCHED) return fail(BNS_E_INVALID_ARG, "autotuning applies to the batched form");
+    for (int32_t k = 0; k < n_problems; ++k)
+        if (!ds[k]) return fail(BNS_E_INVALID_ARG, "dataset %d is NULL", k);
+    const int reps = trials ? trials : 3;
+    // workload key: sizes, alphas (bits), depths, precision
+    std::vector<int64_t> key;
+    key.push_back(o.precision);
+    for (int32_t k = 0; k < n_problems; ++k) {
+        int64_t ab;
+        std::memcpy(&ab, &alpha[k], sizeof(ab));
+        key.insert(key.end(), {ds[k]->n, ds[k]->m, ab, max_depth[k]});
+    }
+    const int device = ds[0]->device;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const TuneEntry &e : g_tune)
+            if (e.device == device && e.key == key) {
+                *best = e.best;
+                best->stream = o.stream;
+                return BNS_OK;
+            }
+    }
+    std::vector<bns_skeleton *> outs((size_t)n_problems, nullptr);
+    auto timed = [&](const bns_options &c, double *sec) -> bns_status {
+        std::vector<double> t;
+        for (int r = 0; r < reps + 1; ++r) {  // first run warms caches and graphs
+            const auto t0 = std::chrono::steady_clock::now();
+            bns_status s2 = bns_pc_skeleton_batch(ds, n_problems, alpha, max_depth, &c, outs.data());
+            const auto t1 = std::chrono::steady_clock::now();
+            for (auto *h : outs) bns_skeleton_free(h);
+            if (s2 != BNS_OK) return s2;
+            if (r > 0) t.push_back(std::chrono::duration<double>(t1 - t0).count());
+        }
+        std::sort(t.begin(), t.end());
+        *sec = t[t.size() / 2];
+        return BNS_OK;
+    };
+    bns_options cur = o;
+    double cur_t = 0.0;
+    st = timed(cur, &cur_t);
+    if (st != BNS_OK) return st;
+    // one option at a time, keeping each improvement
+    const int32_t groups[] = {0, 1, 2};
+    const int32_t reps_opts[] = {0, 16, 64};
+    const int32_t lds_opts[] = {0, 32768, 49152};
+    const int32_t grab_opts[] = {0, 1, 2};
+    for (int knob = 0; knob < 4; ++knob) {
+        for (int v = 0; v < 3; ++v) {
+            bns_options c = cur;
+            if (knob == 0) { if (o.test_group) continue; c.test_group = groups[v]; }
+            if (knob == 1) { if (o.max_replicas) continue; c.max_replicas = reps_opts[v]; }
+            if (knob == 2) { if (o.lds_bytes) continue; c.lds_bytes = lds_opts[v]; }
+            if (knob == 3) { if (o.tickets_per_grab) continue; c.tickets_per_grab = grab_opts[v]; }
+            if (std::memcmp(&c, &cur, sizeof(c)) == 0) continue;
+            double t = 0.0;
+            st = timed(c, &t);
+            if (st != BNS_OK) return st;
+            if (t < cur_t * 0.98) {  // keep only clear gains
+                cur = c;
+                cur_t = t;
+            }
+        }
+    }
+    *best = cur;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.push_back(TuneEntry{device, key, cur});
     return BNS_OK;
 }
 

@@ -169,3 +169,22 @@ def test_wrap_device_and_caller_stream(bns):
     with pytest.raises(bns.BnsError) as ei:
         bns.bns_dataset_wrap_device(bad, ds.n_samples, ds.cards)
     assert "sample 17" in str(ei.value)
+
+
+def test_autotune_options_keep_results(bns):
+    # The autotuner only chooses launch options: searches with its choice
+    # match the oracle, and a second call for the same workload is cached.
+    import time
+    g = load_golden(1)["datasets"][0]
+    ds = _cfg(1)[0]
+    h = bns.bns_dataset_create(ds.data, ds.cards)
+    print("autotune cfg1", flush=True)
+    best = bns.bns_autotune([h], [ds.alpha], [ds.max_depth], trials=1)
+    assert best.test_group in (0, 1, 2) and best.max_replicas in (0, 16, 64)
+    t0 = time.perf_counter()
+    again = bns.bns_autotune([h], [ds.alpha], [ds.max_depth], trials=1)
+    assert time.perf_counter() - t0 < 0.05
+    assert (again.test_group, again.max_replicas, again.lds_bytes, again.tickets_per_grab) == \
+        (best.test_group, best.max_replicas, best.lds_bytes, best.tickets_per_grab)
+    got = bns.bns_pc_skeleton_dataset(h, ds.alpha, ds.max_depth, best)
+    compare_skeleton(got, g, "cfg1 autotuned")
