@@ -20,6 +20,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TIMING_SEARCHES = 5
 
 
 def _sum(stats, key):
@@ -46,6 +47,34 @@ def cpu_baseline(datasets, budget_s=10.0):
             break
     return dict(value=tests / el, unit="CI tests/s", cores=1, kind="oracle",
                 sample=f"{runs} full run(s) of the workload, single thread, {el:.1f} s")
+
+
+def kernel_sources_sha256():
+    """Digest of the HIP sources of the library (csrc/*.hip, *.h)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2212_04259_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per test launch from the committed rocprofv3 counter summary
+    of this workload (FETCH_SIZE + WRITE_SIZE, calibrated against a copy of
+    known size), or None when there is none or the kernels have changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"k_depth_tests_{workload}_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def precision_report(bns, handle, ds, per_depth=2000, seed=7):
@@ -91,6 +120,8 @@ def main():
                     help="smallest sample chunk of split tests (0 default, -1 never split)")
     ap.add_argument("--units-per-group", type=int, default=0)
     ap.add_argument("--test-group", type=int, default=0, help="0 auto, 1 wave, 2 workgroup")
+    ap.add_argument("--max-replicas", type=int, default=0)
+    ap.add_argument("--tickets-per-grab", type=int, default=0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
@@ -130,7 +161,8 @@ def main():
     maxd = [d.max_depth for d in dss]
     knobs = dict(precision=a.precision, lds_bytes=a.lds_bytes, wg_per_cu=a.wg_per_cu,
                  split_min_samples=a.split_min, units_per_group=a.units_per_group,
-                 test_group=a.test_group)
+                 test_group=a.test_group, max_replicas=a.max_replicas,
+                 tickets_per_grab=a.tickets_per_grab)
     opt = bns.bns_options_default(**knobs)
     tuned = None
     if not a.no_autotune:
@@ -157,17 +189,21 @@ def main():
     el = time.perf_counter() - t0
     ms = 1e3 * el / a.steps
 
-    # Counters of one more (untimed) step, with events around each depth's
-    # persistent test launch for the roofline of that kernel.
+    # Counters of a few more (untimed) searches, with HIP events around each
+    # depth's persistent test launch (on the launch stream) for the roofline
+    # of that kernel; the kernel time is the mean over these searches.
     topt = bns.bns_options_default(timing=1, **knobs)
-    hs = step(topt)
-    sks = [bns.collect(h) for h in hs]
+    ksecs = []
+    for _ in range(TIMING_SEARCHES):
+        hs = step(topt)
+        sks = [bns.collect(h) for h in hs]
+        ksecs.append(_sum(sks[0].stats, "kernel_seconds"))
     stats = sks[0].stats          # a multi-dataset search shares one set of counters
     required = _sum(stats, "tests_required")
     executed = _sum(stats, "tests_executed")
     rechecks = _sum(stats, "rechecks")
     obytes = _sum(stats, "operand_bytes")
-    ksec = _sum(stats, "kernel_seconds")
+    ksec = sum(ksecs) / len(ksecs)
     m_total = sum(d.n_samples for d in dss)
     rows_per_test = m_total / len(dss)
     launches = len(stats)
@@ -210,7 +246,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": None,
+            "traffic": measured_traffic(CONFIGS[a.config]["name"]),
             "launches": launches,
             "kernel_ms_per_step": ksec * 1e3,
             "operand_bytes_per_step": obytes,

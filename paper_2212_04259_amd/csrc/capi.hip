@@ -562,10 +562,10 @@ static const size_t kSpecPoolWords = 64u << 10;
 // one executable graph; the depth index lives in the device control block, so
 // the same graph serves every starting depth.
 static bns_status depth_graph(DevCtx &dc, const DepthArgs &a, int grid, int K, hipStream_t s,
-                              hipGraphExec_t *out) {
+                              GraphEntry **out) {
     for (auto &g : dc.graphs)
         if (g->K == K && g->grid == grid && std::memcmp(&g->args, &a, sizeof(a)) == 0) {
-            *out = g->exec;
+            *out = g.get();
             return BNS_OK;
         }
     std::unique_ptr<GraphEntry> g(new GraphEntry());
@@ -584,7 +584,7 @@ static bns_status depth_graph(DevCtx &dc, const DepthArgs &a, int grid, int K, h
     HIP_TRY(e2);
     HIP_TRY(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
     if (dc.graphs.size() >= 8) dc.graphs.erase(dc.graphs.begin());
-    *out = g->exec;
+    *out = g.get();
     dc.graphs.push_back(std::move(g));
     return BNS_OK;
 }
@@ -707,25 +707,26 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
 
     HIP_TRY(launch_init_search(a, s));
 
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (o.timing) {
-        HIP_TRY(hipEventCreate(&ev0));
-        HIP_TRY(hipEventCreate(&ev1));
-    }
+    // Timing: the depth sequences of a launch are enqueued directly, each test
+    // kernel launched with a start/stop event pair, and synchronised once.
     struct EvGuard {
-        hipEvent_t a, b;
+        std::vector<hipEvent_t> v;
         ~EvGuard() {
-            if (a) (void)hipEventDestroy(a);
-            if (b) (void)hipEventDestroy(b);
+            for (hipEvent_t e : v) (void)hipEventDestroy(e);
         }
-    } evg{ev0, ev1};
+    } evg;
+    if (o.timing) {
+        evg.v.assign(2 * (size_t)kDepthsPerLaunch, nullptr);
+        for (hipEvent_t &e : evg.v) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+    }
 
     // Depths run in launches of up to kDepthsPerLaunch depth sequences; the
     // host reads the control block once per launch.  A depth with no tests
     // marks the search done and the kernels of any later sequence in the same
     // launch return at once.
-    const bool use_graph = o.use_graph && !o.timing;
-    const int per_launch = use_graph ? kDepthsPerLaunch : 1;
+    const bool use_graph = o.use_graph != 0 && !o.timing;
+    GraphEntry *ge = nullptr;
+    const int per_launch = (use_graph || o.timing) ? kDepthsPerLaunch : 1;
     std::vector<bns_depth_stats> stats;
     unsigned long long alive = (unsigned long long)pairs_total;  // edges alive at depth d
     unsigned long long pool_used = 0;
@@ -759,16 +760,16 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
             a.pool = dc.pool.as<int32_t>();
         }
         if (use_graph) {
-            hipGraphExec_t exec = nullptr;
-            st = depth_graph(dc, a, grid, K, s, &exec);
+            st = depth_graph(dc, a, grid, K, s, &ge);
             if (st != BNS_OK) return st;
-            HIP_TRY(hipGraphLaunch(exec, s));
+            HIP_TRY(hipGraphLaunch(ge->exec, s));
         } else {
-            HIP_TRY(launch_depth_prepare(a, s));
-            if (o.timing) HIP_TRY(hipEventRecord(ev0, s));
-            HIP_TRY(launch_depth_tests(a, grid, s));
-            if (o.timing) HIP_TRY(hipEventRecord(ev1, s));
-            HIP_TRY(launch_depth_apply(a, s));
+            for (int i = 0; i < K; ++i) {
+                HIP_TRY(launch_depth_prepare(a, s));
+                if (o.timing) HIP_TRY(launch_depth_tests(a, grid, s, evg.v[2 * i], evg.v[2 * i + 1]));
+                else HIP_TRY(launch_depth_tests(a, grid, s));
+                HIP_TRY(launch_depth_apply(a, s));
+            }
         }
         HIP_TRY(hipMemcpyAsync(dc.h_ctl, dc.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         // Results travel in the same round trip when they are small (most
@@ -804,7 +805,7 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
             r.operand_bytes = sd.operand_bytes;
             if (o.timing) {
                 float ms = 0.f;
-                HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
+                HIP_TRY(hipEventElapsedTime(&ms, evg.v[2 * (dd - d)], evg.v[2 * (dd - d) + 1]));
                 r.kernel_seconds = ms * 1e-3;
             }
             stats.push_back(r);

@@ -56,7 +56,10 @@ struct DepthArgs {
 constexpr int kSmallBitWords = 4096;
 __host__ __device__ bool small_search(const DepthArgs &a);
 hipError_t launch_depth_prepare(const DepthArgs &a, hipStream_t s);   // snapshot .. scatter
-hipError_t launch_depth_tests(const DepthArgs &a, int grid, hipStream_t s);
+// With start/stop events the runtime records them with the kernel's own
+// dispatch (tight bracketing of short kernels).
+hipError_t launch_depth_tests(const DepthArgs &a, int grid, hipStream_t s,
+                              hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 hipError_t launch_depth_apply(const DepthArgs &a, hipStream_t s);     // removals + finalize
 hipError_t launch_init_search(const DepthArgs &a, hipStream_t s);     // complete graph, reset
 int depth_tests_max_wg_per_cu(int lds_bytes);

@@ -1,6 +1,8 @@
 // gfx950 kernels of the batched G^2 CI-test engine and of the per-depth
 // PC-stable pipeline (Algorithm 1; grouping, lexicographic conditioning sets
 // and depth-0 handling of Sections IV-B and IV-C).
+#include <hip/hip_ext.h>
+
 #include "device_ci.h"
 #include "kernels.h"
 
@@ -1234,8 +1236,13 @@ hipError_t launch_depth_prepare(const DepthArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_depth_tests(const DepthArgs &a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_depth_tests, dim3(grid), dim3(kWG), (size_t)a.tile.lds_words * 4u, s, a);
+hipError_t launch_depth_tests(const DepthArgs &a, int grid, hipStream_t s, hipEvent_t start,
+                              hipEvent_t stop) {
+    if (start && stop)
+        hipExtLaunchKernelGGL(k_depth_tests, dim3(grid), dim3(kWG), (size_t)a.tile.lds_words * 4u, s,
+                              start, stop, 0, a);
+    else
+        hipLaunchKernelGGL(k_depth_tests, dim3(grid), dim3(kWG), (size_t)a.tile.lds_words * 4u, s, a);
     return hipGetLastError();
 }
 
