@@ -179,7 +179,10 @@ typedef struct bns_depth_stats {
     int64_t rechecks;        /* FP32 decisions re-evaluated in FP64 */
     int64_t tickets;         /* work items scheduled (batched form) */
     double operand_bytes;    /* sum over executed tests of (d + 2) * n_samples */
-    double kernel_seconds;   /* test-launch device time (opt->timing), else 0 */
+    double kernel_seconds;   /* test-launch time from HIP events around the launch
+                                (opt->timing; includes the dispatch gap), else 0 */
+    double span_seconds;     /* test-kernel execution span from device clock stamps:
+                                first workgroup start to last workgroup end (always) */
 } bns_depth_stats;
 
 /* Learns the skeleton of one dataset.  alpha in (0, 1); max_depth >= -1

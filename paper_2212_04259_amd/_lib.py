@@ -62,7 +62,8 @@ class bns_depth_stats(ctypes.Structure):
                 ("edges", ctypes.c_int64), ("tests_required", ctypes.c_int64),
                 ("tests_executed", ctypes.c_int64), ("removed", ctypes.c_int64),
                 ("rechecks", ctypes.c_int64), ("tickets", ctypes.c_int64),
-                ("operand_bytes", ctypes.c_double), ("kernel_seconds", ctypes.c_double)]
+                ("operand_bytes", ctypes.c_double), ("kernel_seconds", ctypes.c_double),
+                ("span_seconds", ctypes.c_double)]
 
 
 _lib = None

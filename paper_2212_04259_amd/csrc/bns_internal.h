@@ -58,6 +58,8 @@ struct DepthStatDev {
     unsigned long long rechecks;
     unsigned long long tickets;
     double operand_bytes;
+    unsigned long long t_start_inv;  // ~(earliest workgroup start), 100 MHz device clock
+    unsigned long long t_end;        // latest workgroup end
 };
 
 // Device-resident control block of a skeleton search.

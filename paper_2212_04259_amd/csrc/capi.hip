@@ -174,6 +174,7 @@ struct DevCtx {
         return e;
     }
     int lds_per_cu = 0;
+    int wall_khz = 0;  // device wall-clock rate
 };
 
 static std::mutex g_ctx_mu;
@@ -194,6 +195,9 @@ static bns_status get_ctx(int device, DevCtx **out) {
                                   device));
     HIP_TRY(hipDeviceGetAttribute(&c->lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
                                   device));
+    if (hipDeviceGetAttribute(&c->wall_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess ||
+        c->wall_khz <= 0)
+        c->wall_khz = 100000;
     HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     HIP_TRY(hipHostMalloc((void **)&c->h_out, sizeof(CiOutDev), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void **)&c->h_ctl, sizeof(Ctl), hipHostMallocDefault));
@@ -803,6 +807,10 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
             r.rechecks = (int64_t)sd.rechecks;
             r.tickets = (int64_t)sd.tickets;
             r.operand_bytes = sd.operand_bytes;
+            if (sd.t_end && sd.t_start_inv) {
+                const unsigned long long t0 = ~sd.t_start_inv;
+                if (sd.t_end > t0) r.span_seconds = (double)(sd.t_end - t0) / (1e3 * dc.wall_khz);
+            }
             if (o.timing) {
                 float ms = 0.f;
                 HIP_TRY(hipEventElapsedTime(&ms, evg.v[2 * (dd - d)], evg.v[2 * (dd - d) + 1]));

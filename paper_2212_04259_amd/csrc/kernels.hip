@@ -867,6 +867,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
     __shared__ double tal_bytes[kWaves];
     Ctl *c = A.ctl;
     if (c->done || c->error) return;
+    if (threadIdx.x == 0 && c->depth < kMaxDepths)
+        atomicMax(&c->stats[c->depth].t_start_inv, ~(unsigned long long)wall_clock64());
     if (threadIdx.x < kWaves) {
         tal_exec[threadIdx.x] = 0;
         tal_re[threadIdx.x] = 0;
@@ -1024,6 +1026,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
         if (tal_exec[k]) atomicAdd(&c->stats[d].executed, tal_exec[k]);
         if (tal_re[k]) atomicAdd(&c->stats[d].rechecks, tal_re[k]);
         if (tal_bytes[k] > 0.0) atomicAdd(&c->stats[d].operand_bytes, tal_bytes[k]);
+        if (k == 0) atomicMax(&c->stats[d].t_end, (unsigned long long)wall_clock64());
     }
 }
 
