@@ -182,7 +182,8 @@ typedef struct bns_depth_stats {
     double kernel_seconds;   /* test-launch time from HIP events around the launch
                                 (opt->timing; includes the dispatch gap), else 0 */
     double span_seconds;     /* test-kernel execution span from device clock stamps:
-                                first workgroup start to last workgroup end (always) */
+                                entry of workgroup 0 (dispatched first) to the end of
+                                the last workgroup (always) */
 } bns_depth_stats;
 
 /* Learns the skeleton of one dataset.  alpha in (0, 1); max_depth >= -1

@@ -19,6 +19,9 @@ constexpr int kMaxLevels = 64;      // ticket levels: level L holds test ranks [
 constexpr uint32_t kMaxCells = 1u << 24;  // largest contingency table (cells)
 constexpr int kMaxDepths = 64;      // depth records kept per search
 constexpr int kSlotsPerWave = 8;    // tickets decoded per grab, per wave
+constexpr int kGrabParts = 8;       // work-unit counters of the test kernel (one per XCD's workgroups)
+constexpr int kGrabStride = 16;     // 64-bit words between two counters (one 128-byte line each)
+constexpr int kBinomLds = 512;      // binomial entries of a depth staged for the test kernel
 
 // Status codes written by kernels into the control block.
 enum DevError : int32_t { kDevOk = 0, kDevTableTooLarge = 1, kDevTooManyTests = 2, kDevDepthTooLarge = 3 };
@@ -58,7 +61,7 @@ struct DepthStatDev {
     unsigned long long rechecks;
     unsigned long long tickets;
     double operand_bytes;
-    unsigned long long t_start_inv;  // ~(earliest workgroup start), 100 MHz device clock
+    unsigned long long t_start;      // entry of the test kernel's workgroup 0, 100 MHz device clock
     unsigned long long t_end;        // latest workgroup end
 };
 
@@ -70,7 +73,6 @@ struct Ctl {
     int32_t pad0;
     unsigned long long n_edges;        // edges in the current list
     unsigned long long total_tickets;
-    unsigned long long ticket_ctr;
     unsigned long long pool_used;      // sepset members written so far
     unsigned int apply_done;           // blocks of the removal kernel that finished
     int32_t maxdeg;                    // largest frozen adjacency set at this depth
@@ -84,7 +86,15 @@ struct Ctl {
     unsigned long long level_cnt[kMaxLevels + 1];
     unsigned int hist[kMaxLevels + 2];
     unsigned int cursor[kMaxLevels + 2];
+    // Binomials C(n, k), n <= maxdeg, k <= depth, row stride depth + 1, for
+    // the test kernel's unranking (bstride 0: not staged, use the full table).
+    int32_t bstride, brows;
+    uint64_t bslice[kBinomLds];
     DepthStatDev stats[kMaxDepths];
+    // Work-unit counters of the test kernel: after every group's first batch
+    // (taken without a counter), unit S0 + p + kGrabParts * i is the i-th of
+    // counter p.  One line each: same-address atomics serialise.
+    alignas(128) unsigned long long grab_ctr[kGrabParts * kGrabStride];
 };
 
 // One CI test for the batch entry point.

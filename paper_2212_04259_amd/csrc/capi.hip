@@ -558,6 +558,9 @@ static const int64_t kSplitWords = 8 << 20;
 static const int64_t kSplitTickets = 32768;
 static const int32_t kSplitMinDefault = 4096;
 static const int32_t kUnitsPerGroupDefault = 1;
+// Column bytes of a search above which the test kernel deals tickets to its
+// grab counters in runs (a quarter of MI355X's 256 MB last-level cache).
+static const double kGrabRunBytes = 64.0 * 1024 * 1024;
 // Results downloaded with the control block after each launch when they fit.
 static const size_t kSpecBytes = 4u << 20;
 static const size_t kSpecPoolWords = 64u << 10;
@@ -606,6 +609,7 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     std::vector<int32_t> var2prob;
     std::vector<uint8_t> gcards;
     int64_t adj_total = 0, pairs_total = 0, m_max = 1, bit_total = 0;
+    double col_bytes = 0.0;  // bytes of all columns
     int32_t G = 0, nmax = 0, dmax = -1;
     bool unbounded = false;
     for (int32_t k = 0; k < P; ++k) {
@@ -616,6 +620,7 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
         for (int32_t v = 0; v < d->n; ++v) var2prob.push_back(k);
         gcards.insert(gcards.end(), d->cards.begin(), d->cards.end());
         G += d->n;
+        col_bytes += (double)d->n * (double)d->m;
         adj_total += (int64_t)d->n * d->n;
         pairs_total += (int64_t)d->n * (d->n - 1) / 2;
         nmax = std::max(nmax, d->n);
@@ -701,6 +706,10 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     a.units_per_group = o.units_per_group == 0 ? kUnitsPerGroupDefault : o.units_per_group;
     a.mode_policy = o.test_group;
     a.grab_fixed = o.tickets_per_grab;
+    // Columns beyond a quarter of the last-level cache: deal the tickets to
+    // the grab counters in runs of 64 (edges that share a column run on one
+    // XCD); else one at a time.
+    a.grab_block_log2 = col_bytes > kGrabRunBytes ? kGrabRunLog2 : 0;
 
     const int lds_bytes = tile.lds_words * 4;
     int wg = o.wg_per_cu ? o.wg_per_cu : depth_tests_max_wg_per_cu(lds_bytes);
@@ -807,8 +816,8 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
             r.rechecks = (int64_t)sd.rechecks;
             r.tickets = (int64_t)sd.tickets;
             r.operand_bytes = sd.operand_bytes;
-            if (sd.t_end && sd.t_start_inv) {
-                const unsigned long long t0 = ~sd.t_start_inv;
+            if (sd.t_end && sd.t_start) {
+                const unsigned long long t0 = sd.t_start;
                 if (sd.t_end > t0) r.span_seconds = (double)(sd.t_end - t0) / (1e3 * dc.wall_khz);
             }
             if (o.timing) {

@@ -263,7 +263,7 @@ struct TermCfg<double> {
 };
 
 template <typename Real>
-BNS_INLINE Real g2_half_term(uint32_t N, uint32_t nxz, uint32_t nyz, uint32_t nzz) {
+BNS_INLINE Real g2_half_term_exact(uint32_t N, uint32_t nxz, uint32_t nyz, uint32_t nzz) {
     if (N == 0) return (Real)nxz * (Real)nyz / (Real)nzz;
     const uint64_t a = (uint64_t)N * nzz;
     const uint64_t b = (uint64_t)nxz * nyz;
@@ -278,6 +278,33 @@ BNS_INLINE Real g2_half_term(uint32_t N, uint32_t nxz, uint32_t nyz, uint32_t nz
     }
     const Real w = (Real)b / (Real)a;
     return (Real)N * (w - (Real)1 - log(w));
+}
+
+template <typename Real>
+BNS_INLINE Real g2_half_term(uint32_t N, uint32_t nxz, uint32_t nyz, uint32_t nzz) {
+    return g2_half_term_exact<Real>(N, nxz, nyz, nzz);
+}
+
+// FP32 form with short arithmetic: a and b are formed exactly in FP64 while
+// both stay below 2^53, so a - b carries no cancellation error and t has a
+// few ulp of relative error; quotients use the hardware reciprocal and the
+// logarithm the hardware log2 (about 1 ulp each).
+template <>
+BNS_INLINE float g2_half_term<float>(uint32_t N, uint32_t nxz, uint32_t nyz, uint32_t nzz) {
+    if (N == 0) return (float)nxz * (float)nyz * __builtin_amdgcn_rcpf((float)nzz);
+    const double a = (double)N * (double)nzz;
+    const double b = (double)nxz * (double)nyz;
+    if (a >= 9007199254740992.0 || b >= 9007199254740992.0) return g2_half_term_exact<float>(N, nxz, nyz, nzz);
+    const float t = (float)(a - b) * __builtin_amdgcn_rcpf((float)(a + b));
+    if (fabsf(t) <= TermCfg<float>::tau) {
+        const float u = t * t;
+        float sr = 1.0f / (float)(2 * TermCfg<float>::terms + 1);
+#pragma unroll
+        for (int k = TermCfg<float>::terms - 1; k >= 1; --k) sr = sr * u + 1.0f / (float)(2 * k + 1);
+        return (float)N * (2.0f * u * __builtin_amdgcn_rcpf(1.0f + t) + 2.0f * t * u * sr);
+    }
+    const float w = (float)b * __builtin_amdgcn_rcpf((float)a);
+    return (float)N * (w - 1.0f - __logf(w));
 }
 
 // ---------------------------------------------------------------------------
@@ -577,21 +604,22 @@ BNS_INLINE void marginals(const Grp &g, const uint32_t *tab, uint32_t *rows, uin
     g.sync();
 }
 
-// This lane's part of the sum of g2_half_term over a chunk.
+// This lane's part of the sum of g2_half_term over a chunk: one cell per
+// lane and step (a table with no more cells than lanes costs one term).
 template <typename Real>
 BNS_INLINE Real g2_partial(const Grp &g, const uint32_t *tab, const uint32_t *rows,
                            const uint32_t *cols, const uint32_t *strata, uint32_t rx, uint32_t ry,
                            uint32_t Zc) {
-    const float inv_ry = 1.0f / (float)ry;
+    const float inv_rx = 1.0f / (float)rx, inv_ry = 1.0f / (float)ry;
+    const uint32_t T = rx * ry * Zc;
     Real acc = 0;
-    for (uint32_t rho = g.rank; rho < ry * Zc; rho += g.size) {
+    for (uint32_t c = g.rank; c < T; c += g.size) {
+        const uint32_t rho = fast_div(c, rx, inv_rx);  // y + ry z
+        const uint32_t xv = c - rho * rx;
         const uint32_t z = fast_div(rho, ry, inv_ry);
         const uint32_t nzz = strata[z];
         if (nzz == 0) continue;
-        const uint32_t nyz = cols[rho];
-        const uint32_t *trow = tab + rx * rho;
-        const uint32_t *mrow = rows + rx * z;
-        for (uint32_t xv = 0; xv < rx; ++xv) acc += g2_half_term<Real>(trow[xv], mrow[xv], nyz, nzz);
+        acc += g2_half_term<Real>(tab[c], rows[xv + rx * z], cols[rho], nzz);
     }
     return acc;
 }
@@ -753,12 +781,13 @@ BNS_INLINE double g2_fp64_resident(const Grp &g, TestSh &t, const Plan &P, const
 }
 
 // Relative error bound of the FP32 G^2 sum: every summand is non-negative and
-// carries a few ulp of error, and each lane adds up to ceil(cells/lanes) of
-// them before a tree, so the relative error stays below
-// (16 + cells/lanes) * 2^-24 per pass.
+// carries at most a few tens of ulp of error (conversions, reciprocals, the
+// series or the log2), and each lane adds up to ceil(cells/lanes) of them
+// before a tree, so the relative error stays below (32 + cells/lanes) * 2^-24
+// per pass.
 BNS_INLINE double fp32_g2_rel_bound(const Plan &P, int S) {
     const double per_lane = (double)(P.rxy * P.zc_per) / (double)S + 1.0;
-    return (16.0 + per_lane) * 5.96e-8 * (double)P.nchunks + 1e-6;
+    return (32.0 + per_lane) * 5.96e-8 * (double)P.nchunks + 1e-6;
 }
 
 // Tail of the group (chi2_tail_wave needs a whole wave; a workgroup lets its

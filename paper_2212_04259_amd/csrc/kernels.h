@@ -49,11 +49,14 @@ struct DepthArgs {
     int32_t units_per_group;  // work units aimed for per concurrent group when splitting
     int32_t mode_policy;      // 0 automatic, 1 one test per wave, 2 one test per workgroup
     int32_t grab_fixed;       // tickets per grab (0: from the ticket count)
+    int32_t grab_block_log2;  // test kernel: units dealt to a grab counter in runs of 2^this (0 or kGrabRunLog2)
+    int32_t pad2;
 };
 
 // Small searches keep the adjacency as bit rows in LDS and prepare each depth
 // inside the removal kernel of the depth before.
 constexpr int kSmallBitWords = 4096;
+constexpr int kGrabRunLog2 = 6;  // runs of 64 tickets per grab counter (large searches)
 __host__ __device__ bool small_search(const DepthArgs &a);
 hipError_t launch_depth_prepare(const DepthArgs &a, hipStream_t s);   // snapshot .. scatter
 // With start/stop events the runtime records them with the kernel's own

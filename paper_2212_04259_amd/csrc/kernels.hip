@@ -102,7 +102,6 @@ __global__ void k_init_search(DepthArgs A) {
             c->error = 0;
             c->n_edges = 0;
             c->total_tickets = 0;
-            c->ticket_ctr = 0;
             c->pool_used = 0;
             c->apply_done = 0;
         }
@@ -187,7 +186,6 @@ __global__ __launch_bounds__(kWG) void k_scan_rows(DepthArgs A) {
         int m2 = 0;
         for (int i = 0; i < kWG; ++i) m2 = max(m2, mdeg[i]);
         c->maxdeg = m2;
-        c->ticket_ctr = 0;
         c->total_tickets = 0;
         if (c->depth >= kMaxDepths) c->error = kDevDepthTooLarge;
     }
@@ -277,9 +275,18 @@ __global__ __launch_bounds__(kWG) void k_edges(DepthArgs A) {
 // Tickets per test wave from which one test per wave beats one per workgroup.
 constexpr unsigned long long kWaveModeRounds = 6;
 
-BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist, int d,
+BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist, int d, int maxdeg,
                             unsigned int *cursor_lds = nullptr, int *done_lds = nullptr) {
     const int lane = threadIdx.x & 63;
+    // binomial slice of the depth for the test kernel, work-unit counters
+    const int brows = maxdeg + 1;
+    const bool staged = d + 1 <= kBinomK && brows <= A.binom_rows && brows * (d + 1) <= kBinomLds;
+    if (staged)
+        for (int i = lane; i < brows * (d + 1); i += 64) {
+            const int n = i / (d + 1), k = i - n * (d + 1);
+            c->bslice[i] = A.binom[n * kBinomK + k];
+        }
+    if (lane < kGrabParts) c->grab_ctr[lane * kGrabStride] = 0ull;
     // cursor[lv] = number of edges with more than lv levels (bucket start in
     // the descending order); lanes hold lv = lane and lv = 64, 65 go to lane 0.
     const unsigned int h = hist[lane];
@@ -326,7 +333,8 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
         c->level_cnt[kMaxLevels] = 0;
         if (any_bad) c->error = kDevTooManyTests;
         c->total_tickets = any_bad ? 0ull : total;
-        c->ticket_ctr = 0;
+        c->bstride = staged ? d + 1 : 0;
+        c->brows = staged ? brows : 0;
         // Group per test: a wave (no workgroup barriers), or a workgroup
         // (4x the LDS and lanes per test: shorter tests, less speculation).
         // Automatic: a workgroup per test unless there are tickets for
@@ -382,7 +390,7 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
 __global__ void k_levels(DepthArgs A) {
     Ctl *c = A.ctl;
     if (c->done) return;
-    levels_wave(A, c, c->hist, c->depth);
+    levels_wave(A, c, c->hist, c->depth, c->maxdeg);
 }
 
 // Scatter into level order and reset the per-edge first-accept ranks.  The
@@ -613,7 +621,6 @@ BNS_INLINE void prepare_block(const DepthArgs &A, Ctl *c, int d, SmallSh &sh) {
     if (threadIdx.x == 0) {
         c->n_edges = E;
         c->maxdeg = maxdeg;
-        c->ticket_ctr = 0;
         c->total_tickets = 0;
         if (d >= kMaxDepths) c->error = kDevDepthTooLarge;
     }
@@ -636,7 +643,7 @@ BNS_INLINE void prepare_block(const DepthArgs &A, Ctl *c, int d, SmallSh &sh) {
         }
     }
     __syncthreads();
-    if (w == 0) levels_wave(A, c, sh.hist, d, sh.cursor, &sh.done);
+    if (w == 0) levels_wave(A, c, sh.hist, d, maxdeg, sh.cursor, &sh.done);
     __syncthreads();
     if (sh.done) return;
     // pass 2: edge records in level order, one thread per row word
@@ -722,7 +729,6 @@ struct Desc {
     uint8_t card[kMaxCols];
 };
 
-constexpr int kBinomLds = 512;   // binomial entries staged in LDS
 constexpr int kProbsLds = 8;     // problem records staged in LDS (searches of few problems)
 constexpr int kCardsLds = 2048;  // cardinalities staged in LDS (searches of few variables)
 
@@ -763,7 +769,9 @@ BNS_INLINE void decode_ticket(const DepthArgs &A, const unsigned long long *lvl_
     const int L = lo;
     const unsigned long long off = tk - lvl_base[L];
     const unsigned long long cnt = lvl_cnt[L];
-    const unsigned long long jj = off / cnt;
+    // (a 32-bit division when both fit: much shorter than the 64-bit one)
+    const unsigned long long jj = ((off | cnt) >> 32) ? off / cnt
+                                                      : (unsigned long long)((uint32_t)off / (uint32_t)cnt);
     const int64_t e = (int64_t)(off - jj * cnt);
     const unsigned long long r = ((1ull << L) - 1ull) + jj;
     const EdgeRec rec = A.edges[e];
@@ -852,6 +860,69 @@ BNS_INLINE uint64_t table_cells(const TestSh &t) {
     return T;
 }
 
+static_assert(kGrabParts <= 8, "counter indices are packed into 3 bits");
+constexpr int kGrabPartsLog2 = 3;
+static_assert(kGrabParts == 1 << kGrabPartsLog2, "a power of two");
+
+// Dynamic units (those from S0 on) are dealt to the counters in blocks of
+// 2^lgb consecutive units: the i-th unit of counter p is dyn_unit(S0, p, i, lgb).
+BNS_INLINE unsigned long long dyn_unit(unsigned long long S0, int p, unsigned long long i, int lgb) {
+    const unsigned long long blk = i >> lgb, off = i - (blk << lgb);
+    return S0 + ((blk * kGrabParts + (unsigned long long)p) << lgb) + off;
+}
+// Units of counter p below `units`.
+BNS_INLINE unsigned long long dyn_units(unsigned long long units, unsigned long long S0, int p, int lgb) {
+    const unsigned long long D = units > S0 ? units - S0 : 0ull;
+    const int lrow = kGrabPartsLog2 + lgb;  // (shifts: no 64-bit division)
+    const unsigned long long full = D >> lrow, rem = D - (full << lrow);
+    const unsigned long long lo = (unsigned long long)p << lgb;
+    const unsigned long long extra = rem > lo ? min(rem - lo, 1ull << lgb) : 0ull;
+    return (full << lgb) + extra;
+}
+
+BNS_INLINE unsigned long long shfl_xor_u64(unsigned long long v, int off) {
+    const unsigned lo = __shfl_xor((unsigned)(v & 0xffffffffull), off, 64);
+    const unsigned hi = __shfl_xor((unsigned)(v >> 32), off, 64);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Values of the group's rank 0 in every lane of the group (a workgroup goes
+// through `slot` in LDS).
+BNS_INLINE void group_bcast2_u64(const Grp &g, unsigned long long &a, unsigned long long &b,
+                                 unsigned long long (&slot)[2]) {
+    if (!g.block) {
+        a = bcast_u64(a);
+        b = bcast_u64(b);
+        return;
+    }
+    if (threadIdx.x == 0) {
+        slot[0] = a;
+        slot[1] = b;
+    }
+    __syncthreads();
+    a = slot[0];
+    b = slot[1];
+    __syncthreads();
+}
+
+// Header of a depth, read by one thread of each workgroup.
+struct TestHdr {
+    unsigned long long total, units, cap;
+    long long Lc;
+    int32_t quit, d, C, mode, B, bstride, brows, pad;
+};
+
+// Units of a grab: i0 + r (part < 0: the first, static batch) or
+// dyn_unit(S0, part, i0 + r), r < cnt.
+struct Batch {
+    unsigned long long i0;
+    int part, cnt;
+};
+
+// LGB: log2 of the run of consecutive units dealt to a grab counter (a
+// template parameter: the kernel's registers are tight, and the instance for
+// single units keeps the shortest arithmetic).
+template <int LGB>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k_depth_tests(DepthArgs A) {
     extern __shared__ uint32_t lds[];
     __shared__ TestSh tsh[kWaves];
@@ -861,55 +932,73 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
     __shared__ uint64_t btab_lds[kBinomLds];
     __shared__ ProbDev probs_sh[kProbsLds];
     __shared__ uint8_t cards_sh[kCardsLds];
-    __shared__ unsigned long long grab;
+    __shared__ TestHdr hdr;
+    __shared__ unsigned long long grab2[2];
     // per-group tallies (kept in LDS: no vector registers across tests)
     __shared__ unsigned long long tal_exec[kWaves], tal_re[kWaves];
     __shared__ double tal_bytes[kWaves];
     Ctl *c = A.ctl;
-    if (c->done || c->error) return;
-    if (threadIdx.x == 0 && c->depth < kMaxDepths)
-        atomicMax(&c->stats[c->depth].t_start_inv, ~(unsigned long long)wall_clock64());
+    const unsigned long long t_enter = wall_clock64();
+    // Everything the workgroup needs from the control block and the search
+    // set-up is loaded in one round: header, level table, binomial slice,
+    // problem records and cardinalities.
+    if (threadIdx.x == 0) {
+        hdr.quit = (c->done | c->error) != 0;
+        hdr.d = c->depth;
+        hdr.total = c->total_tickets;
+        hdr.units = c->total_units;
+        hdr.C = c->chunks;
+        hdr.Lc = c->chunk_len;
+        hdr.cap = c->split_cap;
+        hdr.mode = c->mode;
+        hdr.B = c->batch;
+        hdr.bstride = c->bstride;
+        hdr.brows = c->brows;
+    }
     if (threadIdx.x < kWaves) {
         tal_exec[threadIdx.x] = 0;
         tal_re[threadIdx.x] = 0;
         tal_bytes[threadIdx.x] = 0.0;
     }
-    const int d = c->depth;
-    const unsigned long long total = c->total_tickets;
-    const unsigned long long units = c->total_units;
-    const int C = c->chunks;
-    const long long Lc = c->chunk_len;
-    const uint64_t cap = c->split_cap;
-    const int mode = c->mode;
-    const int B = c->batch;
     if (threadIdx.x <= kMaxLevels) {
         lvl_base[threadIdx.x] = c->level_base[threadIdx.x];
         lvl_cnt[threadIdx.x] = c->level_cnt[threadIdx.x];
     }
-    // problem records and cardinalities in LDS when they fit (two fewer
-    // dependent loads per ticket decode)
+    for (int i = threadIdx.x; i < kBinomLds; i += kWG) btab_lds[i] = c->bslice[i];
     const bool probs_in_lds = A.n_probs <= kProbsLds;
     const bool cards_in_lds = A.n_globals <= kCardsLds;
     if (probs_in_lds && threadIdx.x < (unsigned)A.n_probs) probs_sh[threadIdx.x] = A.probs[threadIdx.x];
     if (cards_in_lds)
         for (int i = threadIdx.x; i < A.n_globals; i += kWG) cards_sh[i] = A.cards[i];
-    // binomials C(n, k), n <= max degree, k <= d: in LDS when they fit
-    const int brows_need = c->maxdeg + 1;
+    __syncthreads();
+    // (header values are uniform: scalar registers)
+    if (uni(hdr.quit)) return;
+    const int d = uni(hdr.d);
+    // Start of the launch: the entry time of workgroup 0 (dispatched first),
+    // a plain store.  (An atomic per workgroup would queue on one address,
+    // and a wave's next wait for a load also waits for its older stores.)
+    if (blockIdx.x == 0 && threadIdx.x == 0 && d < kMaxDepths) c->stats[d].t_start = t_enter;
+    const unsigned long long total = uni(hdr.total);
+    const unsigned long long units = uni(hdr.units);
+    const int C = uni(hdr.C);
+    const long long Lc = uni(hdr.Lc);
+    const uint64_t cap = uni(hdr.cap);
+    const int mode = uni(hdr.mode);
+    const int B0 = min(max(uni(hdr.B), 1), kSlotsPerWave);
+    // binomials C(n, k), n <= max degree, k <= d: from the staged slice when
+    // it fits, else from the full table
     const uint64_t *btab = A.binom;
     int bstride = kBinomK, brows = A.binom_rows;
-    if (brows_need * (d + 1) <= kBinomLds && brows_need <= A.binom_rows) {
-        for (int i = threadIdx.x; i < brows_need * (d + 1); i += kWG) {
-            const int n = i / (d + 1), k = i - n * (d + 1);
-            btab_lds[i] = A.binom[n * kBinomK + k];
-        }
+    if (uni(hdr.bstride) > 0) {
         btab = btab_lds;
-        bstride = d + 1;
-        brows = brows_need;
+        bstride = uni(hdr.bstride);
+        brows = uni(hdr.brows);
     }
-    __syncthreads();
     int nlev = 0;
     while (nlev < kMaxLevels && lvl_cnt[nlev] > 0) ++nlev;
-    const int w = threadIdx.x >> 6;
+    // (the wave index and every pointer derived from it are wave-uniform:
+    // scalar registers, not vector ones)
+    const int w = uni((int)(threadIdx.x >> 6));
     // mode 0: one test per wave in a quarter of the LDS; mode 1: one test per
     // workgroup in all of it
     const Grp g = mode ? Grp::workgroup() : Grp::wave();
@@ -918,24 +1007,34 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
     const uint32_t W = mode ? (uint32_t)A.tile.lds_words : (uint32_t)A.tile.lds_words / kWaves;
     uint32_t *region = mode ? lds : lds + (uint32_t)w * W;
     const int ti = mode ? 0 : w;  // tally slot of the group
-    // A unit is (ticket, chunk); chunk-major order puts the chunks of one
-    // ticket far apart, so they run on different groups at the same time.
-    unsigned long long base = 0;
-    if (g.rank == 0) base = atomicAdd(&c->ticket_ctr, (unsigned long long)B);
+    // Work units: a unit is (ticket, chunk); chunk-major order puts the
+    // chunks of one ticket far apart, so they run on different groups at the
+    // same time.  Group gid's first batch is units [gid B0, gid B0 + B0),
+    // taken without a counter (the grid is launched with exactly G groups);
+    // the rest are spread over kGrabParts counters, a workgroup starting on
+    // counter blockIdx mod kGrabParts (about one per XCD), so that grabs do
+    // not all queue on one address.  Counters deal units in blocks: single
+    // units (the finest interleave) when the columns stay in the last-level
+    // cache, runs of consecutive tickets (edges that share a column) when
+    // they do not, so that each XCD's L2 sees fewer distinct columns.
+    const int G = mode ? (int)gridDim.x : (int)gridDim.x * kWaves;
+    const int gid = mode ? (int)blockIdx.x : (int)blockIdx.x * kWaves + w;
+    const unsigned long long S0 = (unsigned long long)G * (unsigned long long)B0;
+    int part = (int)(blockIdx.x % kGrabParts);
+    constexpr int lgb = LGB;
+    Batch bt;
+    bt.i0 = (unsigned long long)gid * (unsigned long long)B0;
+    bt.part = -1;
+    bt.cnt = bt.i0 < units ? (int)min((unsigned long long)B0, units - bt.i0) : 0;
+    unsigned long long left_est = dyn_units(units, S0, part, lgb);  // after the last grab
     for (;;) {
-        if (mode) {
-            if (threadIdx.x == 0) grab = base;
-            __syncthreads();
-            base = grab;
-            __syncthreads();
-        } else {
-            base = bcast_u64(base);
-        }
-        if (base >= units) break;
-        const int cnt = (int)min((unsigned long long)B, units - base);
+        const int cnt = bt.cnt;
         if (g.rank < cnt) {
-            const unsigned long long u = base + g.rank;
-            const unsigned long long ch = (C > 1) ? u / total : 0ull;
+            const unsigned long long i = bt.i0 + (unsigned long long)g.rank;
+            const unsigned long long u = bt.part < 0 ? i : dyn_unit(S0, bt.part, i, lgb);
+            const unsigned long long ch = (C <= 1) ? 0ull
+                                          : ((u | total) >> 32) ? u / total
+                                                                : (unsigned long long)((uint32_t)u / (uint32_t)total);
             const unsigned long long tk = u - ch * total;
             Desc &q = mine[g.rank];
             decode_ticket(A, lvl_base, lvl_cnt, nlev, tk, d, btab, bstride, brows, C == 1,
@@ -1017,8 +1116,56 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
             if (chk && mine[j + 1].r > ma_next) mine[j + 1].valid = 0;
             g.sync();
         }
-        base = 0;
-        if (g.rank == 0) base = atomicAdd(&c->ticket_ctr, (unsigned long long)B);
+        // Next grab: B0 units from the group's counter.  Once that counter
+        // is known to be used up, ranks 1..kGrabParts-1 read the other
+        // counters in the same round trip, so that the group moves to the one
+        // with the most units left, or stops.
+        bt.cnt = 0;
+        for (;;) {
+            const unsigned long long np = dyn_units(units, S0, part, lgb);
+            const bool scan = left_est == 0;
+            unsigned long long k = 0, key = 0;
+            if (g.rank == 0) {
+                if (np > 0) k = atomicAdd(&c->grab_ctr[part * kGrabStride], (unsigned long long)B0);
+            } else if (scan && g.rank < kGrabParts) {
+                const int r = (part + g.rank) % kGrabParts;
+                const unsigned long long nr = dyn_units(units, S0, r, lgb);
+                if (nr > 0) {
+                    const unsigned long long kr = __hip_atomic_load(&c->grab_ctr[r * kGrabStride],
+                                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (nr > kr) key = ((nr - kr) << 3) | (unsigned long long)r;
+                }
+            }
+            // the counter with the most units left (ranks 1..kGrabParts-1 are
+            // lanes of the group's first wave)
+            if (scan && (threadIdx.x < 64 || !g.block)) {
+#pragma unroll
+                for (int off = 1; off < kGrabParts; off <<= 1) {
+                    const unsigned long long o = shfl_xor_u64(key, off);
+                    key = o > key ? o : key;
+                }
+            }
+            group_bcast2_u64(g, k, key, grab2);
+            k = uni(k);
+            key = uni(key);
+            if (np > 0 && k < np) {
+                bt.i0 = k;
+                bt.part = part;
+                bt.cnt = (int)min((unsigned long long)B0, np - k);
+                left_est = np - k - (unsigned long long)bt.cnt;
+                break;
+            }
+            // the counter is used up: move to the one with the most units
+            // left (read with this grab, or with the next one), or stop when
+            // none has any
+            if (!scan) {
+                left_est = 0;
+                continue;
+            }
+            if (key == 0) break;
+            part = (int)(key & 7ull);
+        }
+        if (bt.cnt == 0) break;
     }
     __syncthreads();
     if (threadIdx.x < kWaves && d < kMaxDepths) {
@@ -1239,13 +1386,19 @@ hipError_t launch_depth_prepare(const DepthArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Instance for the search: tickets dealt in runs when its columns exceed the
+// last-level cache's share (grab_block_log2 = kGrabRunLog2), else singly.
+static auto depth_tests_kernel(const DepthArgs &a) -> decltype(&k_depth_tests<0>) {
+    return a.grab_block_log2 ? &k_depth_tests<kGrabRunLog2> : &k_depth_tests<0>;
+}
+
 hipError_t launch_depth_tests(const DepthArgs &a, int grid, hipStream_t s, hipEvent_t start,
                               hipEvent_t stop) {
     if (start && stop)
-        hipExtLaunchKernelGGL(k_depth_tests, dim3(grid), dim3(kWG), (size_t)a.tile.lds_words * 4u, s,
+        hipExtLaunchKernelGGL(depth_tests_kernel(a), dim3(grid), dim3(kWG), (size_t)a.tile.lds_words * 4u, s,
                               start, stop, 0, a);
     else
-        hipLaunchKernelGGL(k_depth_tests, dim3(grid), dim3(kWG), (size_t)a.tile.lds_words * 4u, s, a);
+        hipLaunchKernelGGL(depth_tests_kernel(a), dim3(grid), dim3(kWG), (size_t)a.tile.lds_words * 4u, s, a);
     return hipGetLastError();
 }
 
@@ -1256,8 +1409,11 @@ hipError_t launch_depth_apply(const DepthArgs &a, hipStream_t s) {
 }
 
 hipError_t allow_dynamic_lds(int bytes) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_depth_tests,
+    hipError_t e = hipFuncSetAttribute((const void *)k_depth_tests<kGrabRunLog2>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_depth_tests<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                bytes);
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void *)k_ci_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 bytes);
@@ -1269,7 +1425,7 @@ hipError_t allow_dynamic_lds(int bytes) {
 
 int depth_tests_max_wg_per_cu(int lds_bytes) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_depth_tests, kWG, (size_t)lds_bytes) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_depth_tests<0>, kWG, (size_t)lds_bytes) !=
         hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
@@ -1283,7 +1439,7 @@ int depth_tests_fit_lds(int lds_per_cu) {
     const int target = depth_tests_max_wg_per_cu(4096);
     hipFuncAttributes fa;
     int stat = 16384;
-    if (hipFuncGetAttributes(&fa, (const void *)k_depth_tests) == hipSuccess) stat = (int)fa.sharedSizeBytes;
+    if (hipFuncGetAttributes(&fa, (const void *)k_depth_tests<0>) == hipSuccess) stat = (int)fa.sharedSizeBytes;
     if (lds_per_cu <= 0) lds_per_cu = 65536;
     const int share = (lds_per_cu / max(target, 1)) & ~2047;
     int b = (share - stat) & ~255;
