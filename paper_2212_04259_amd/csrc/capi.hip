@@ -122,6 +122,7 @@ struct GraphEntry {
     DepthArgs args;
     int grid = 0;
     int K = 0;
+    bool init = false;  // begins with the search's initialisation
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ~GraphEntry() {
@@ -568,10 +569,10 @@ static const size_t kSpecPoolWords = 64u << 10;
 // Captures (once per distinct argument set) K consecutive depth sequences as
 // one executable graph; the depth index lives in the device control block, so
 // the same graph serves every starting depth.
-static bns_status depth_graph(DevCtx &dc, const DepthArgs &a, int grid, int K, hipStream_t s,
+static bns_status depth_graph(DevCtx &dc, const DepthArgs &a, int grid, int K, bool init, hipStream_t s,
                               GraphEntry **out) {
     for (auto &g : dc.graphs)
-        if (g->K == K && g->grid == grid && std::memcmp(&g->args, &a, sizeof(a)) == 0) {
+        if (g->K == K && g->grid == grid && g->init == init && std::memcmp(&g->args, &a, sizeof(a)) == 0) {
             *out = g.get();
             return BNS_OK;
         }
@@ -579,13 +580,15 @@ static bns_status depth_graph(DevCtx &dc, const DepthArgs &a, int grid, int K, h
     g->args = a;
     g->grid = grid;
     g->K = K;
+    g->init = init;
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipSuccess;
+    hipError_t e = init ? launch_init_search(a, s) : hipSuccess;
     for (int i = 0; i < K && e == hipSuccess; ++i) {
         e = launch_depth_prepare(a, s);
         if (e == hipSuccess) e = launch_depth_tests(a, grid, s);
         if (e == hipSuccess) e = launch_depth_apply(a, s);
     }
+    if (e == hipSuccess) e = launch_publish(a, s);
     hipError_t e2 = hipStreamEndCapture(s, &g->graph);
     HIP_TRY(e);
     HIP_TRY(e2);
@@ -655,7 +658,8 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     HIP_TRY(dc.ipos.ensure(sizeof(int32_t) * (size_t)adj_total));
     // bit rows are used only by small searches (at most kSmallBitWords words)
     HIP_TRY(dc.adjbits.ensure(sizeof(uint64_t) * (size_t)std::min<int64_t>(std::max<int64_t>(bit_total, 1), kSmallBitWords)));
-    HIP_TRY(dc.rdepth.ensure((size_t)adj_total));
+    const size_t rbytes = ((size_t)adj_total + 7) & ~(size_t)7;  // removal depths, padded for 8-byte copies
+    HIP_TRY(dc.rdepth.ensure(rbytes));
     HIP_TRY(dc.deg.ensure(sizeof(int32_t) * (size_t)G));
     HIP_TRY(dc.rowcnt.ensure(sizeof(int32_t) * (size_t)G));
     HIP_TRY(dc.rowbase.ensure(sizeof(int64_t) * (size_t)G));
@@ -718,8 +722,6 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     a.n_pairs = pairs_total;
     a.edge_grid = (int)std::max<int64_t>(1, std::min<int64_t>(512, (pairs_total + kWG - 1) / kWG));
 
-    HIP_TRY(launch_init_search(a, s));
-
     // Timing: the depth sequences of a launch are enqueued directly, each test
     // kernel launched with a start/stop event pair, and synchronised once.
     struct EvGuard {
@@ -743,7 +745,6 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     std::vector<bns_depth_stats> stats;
     unsigned long long alive = (unsigned long long)pairs_total;  // edges alive at depth d
     unsigned long long pool_used = 0;
-    const size_t rbytes = ((size_t)adj_total + 7) & ~(size_t)7;
     bool spec = false;
     size_t spec_pool = 0;
     int d = 0;
@@ -772,30 +773,33 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
             std::swap(dc.pool.bytes, nb.bytes);
             a.pool = dc.pool.as<int32_t>();
         }
+        // The last kernel of a launch writes the control block into pinned
+        // host memory, and when the results are small (most searches finish
+        // within one launch) the removal depths and the first removal records
+        // too: one round trip, no copies.
+        spec_pool = 0;
+        spec = rbytes + sizeof(int32_t) * kSpecPoolWords <= kSpecBytes;
+        if (spec) {
+            spec_pool = std::min<size_t>(kSpecPoolWords, dc.pool.bytes / sizeof(int32_t));
+            HIP_TRY(dc.results(rbytes + sizeof(int32_t) * spec_pool));
+        }
+        a.h_ctl = dc.h_ctl;
+        a.h_res = spec ? (char *)dc.hres : nullptr;
+        a.res_rbytes = (int64_t)rbytes;
+        a.res_pool_words = (int64_t)spec_pool;
         if (use_graph) {
-            st = depth_graph(dc, a, grid, K, s, &ge);
+            st = depth_graph(dc, a, grid, K, d == 0, s, &ge);
             if (st != BNS_OK) return st;
             HIP_TRY(hipGraphLaunch(ge->exec, s));
         } else {
+            if (d == 0) HIP_TRY(launch_init_search(a, s));
             for (int i = 0; i < K; ++i) {
                 HIP_TRY(launch_depth_prepare(a, s));
                 if (o.timing) HIP_TRY(launch_depth_tests(a, grid, s, evg.v[2 * i], evg.v[2 * i + 1]));
                 else HIP_TRY(launch_depth_tests(a, grid, s));
                 HIP_TRY(launch_depth_apply(a, s));
             }
-        }
-        HIP_TRY(hipMemcpyAsync(dc.h_ctl, dc.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-        // Results travel in the same round trip when they are small (most
-        // searches finish within one launch): removal depths and a prefix of
-        // the removal records.
-        spec_pool = 0;
-        spec = rbytes + sizeof(int32_t) * kSpecPoolWords <= kSpecBytes;
-        if (spec) {
-            spec_pool = std::min<size_t>(kSpecPoolWords, dc.pool.bytes / sizeof(int32_t));
-            HIP_TRY(dc.results(rbytes + sizeof(int32_t) * spec_pool));
-            HIP_TRY(hipMemcpyAsync(dc.hres, dc.rdepth.p, (size_t)adj_total, hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipMemcpyAsync((char *)dc.hres + rbytes, dc.pool.p, sizeof(int32_t) * spec_pool,
-                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(launch_publish(a, s));
         }
         HIP_TRY(hipStreamSynchronize(s));
         const Ctl &c = *dc.h_ctl;

@@ -51,6 +51,11 @@ struct DepthArgs {
     int32_t grab_fixed;       // tickets per grab (0: from the ticket count)
     int32_t grab_block_log2;  // test kernel: units dealt to a grab counter in runs of 2^this (0 or kGrabRunLog2)
     int32_t pad2;
+    // Results of a launch, written into pinned host memory by its last kernel.
+    Ctl *h_ctl;               // copy of the control block
+    char *h_res;              // null, or removal depths (res_rbytes) then the first removal records
+    int64_t res_rbytes;       // adjacency bytes rounded up to 8 (rdepth holds at least this many)
+    int64_t res_pool_words;   // removal-record words copied at most
 };
 
 // Small searches keep the adjacency as bit rows in LDS and prepare each depth
@@ -65,6 +70,7 @@ hipError_t launch_depth_tests(const DepthArgs &a, int grid, hipStream_t s,
                               hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 hipError_t launch_depth_apply(const DepthArgs &a, hipStream_t s);     // removals + finalize
 hipError_t launch_init_search(const DepthArgs &a, hipStream_t s);     // complete graph, reset
+hipError_t launch_publish(const DepthArgs &a, hipStream_t s);         // results into pinned host memory
 int depth_tests_max_wg_per_cu(int lds_bytes);
 int depth_tests_fit_lds(int lds_per_cu);  // default dynamic LDS at full occupancy
 hipError_t allow_dynamic_lds(int bytes);  // raises the per-kernel dynamic LDS limit

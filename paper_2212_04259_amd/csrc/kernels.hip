@@ -3,6 +3,8 @@
 // and depth-0 handling of Sections IV-B and IV-C).
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "device_ci.h"
 #include "kernels.h"
 
@@ -284,7 +286,7 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
     if (staged)
         for (int i = lane; i < brows * (d + 1); i += 64) {
             const int n = i / (d + 1), k = i - n * (d + 1);
-            c->bslice[i] = A.binom[n * kBinomK + k];
+            c->bslice[i] = k == 0 ? 1ull : A.binom[n * kBinomK + k];
         }
     if (lane < kGrabParts) c->grab_ctr[lane * kGrabStride] = 0ull;
     // cursor[lv] = number of edges with more than lv levels (bucket start in
@@ -461,6 +463,10 @@ struct SmallSh {
     unsigned long long red[2][kSmallWaves];
     int wmax[kSmallWaves];
     int done;
+    // control-block header, read once
+    int h_done, h_depth, h_maxdeg, h_bstride, h_brows;
+    unsigned long long h_edges;
+    unsigned long long pool_ctr;  // removal-record words used (the removal kernel's own counter)
 };
 
 // Tests of edge (v, u) at depth d from the frozen degrees (0 when the depth
@@ -617,7 +623,7 @@ BNS_INLINE void prepare_block(const DepthArgs &A, Ctl *c, int d, SmallSh &sh) {
         maxdeg = max(maxdeg, sh.wmax[i]);
     }
     for (int x = threadIdx.x; x <= maxdeg && d <= kMaxZ; x += kSmallThreads)
-        sh.bcol[x] = binom_at(A.binom, A.binom_rows, x, d);
+        sh.bcol[x] = d == 0 ? 1ull : binom_at(A.binom, A.binom_rows, x, d);
     if (threadIdx.x == 0) {
         c->n_edges = E;
         c->maxdeg = maxdeg;
@@ -690,18 +696,22 @@ BNS_INLINE void prepare_block(const DepthArgs &A, Ctl *c, int d, SmallSh &sh) {
 __global__ __launch_bounds__(kSmallThreads) void k_prepare_small(DepthArgs A) {
     __shared__ SmallSh sh;
     Ctl *c = A.ctl;
-    if (c->done) return;
+    if (threadIdx.x == 0) {
+        sh.h_done = c->done;
+        sh.h_depth = c->depth;
+    }
     small_load(A, sh);
     __syncthreads();
-    prepare_block(A, c, c->depth, sh);
+    if (sh.h_done) return;
+    prepare_block(A, c, sh.h_depth, sh);
 }
 
 // ---------------------------------------------------------------------------
 // Persistent per-depth test kernel.
 //
-// Tickets come from one counter.  A ticket names (edge, rank r); the
-// conditioning set is unranked on the fly from r (Section IV-C) over the
-// frozen adjacency list of side A (lower id) for r < nA, else side B.  A test
+// A ticket names (edge, rank r); the conditioning set is unranked on the fly
+// from r (Section IV-C) over the frozen adjacency list of side A (lower id)
+// for r < nA, else side B.  A test
 // whose rank exceeds the smallest accepting rank already found for its edge
 // is skipped; since every rank below the final smallest accepting rank is
 // always run, the edge's first accepting set in the sequential order is found
@@ -1188,9 +1198,11 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
 // [problem, i, j, s_1 .. s_d] (d + 3 words), one atomic per wave.
 // One edge per lane (all lanes of the wave call it together; valid marks
 // the lanes that hold an edge).
+// pool_lds (optional): an LDS counter of removal-record words (a removal
+// kernel of one workgroup), instead of the control block's.
 BNS_INLINE void apply_one(const DepthArgs &A, Ctl *c, int d, bool valid, const EdgeRec &r,
                           unsigned long long ma, unsigned long long &rem, const Binom &bn,
-                          const ProbDev *probs, uint64_t *lds_bits) {
+                          const ProbDev *probs, uint64_t *lds_bits, unsigned long long *pool_lds) {
     const int lane = threadIdx.x & 63;
     const uint64_t lt = lanes_below_mask();
     const bool removed = valid && ma != ~0ull;
@@ -1201,7 +1213,8 @@ BNS_INLINE void apply_one(const DepthArgs &A, Ctl *c, int d, bool valid, const E
     if (d > 0) {
         const unsigned long long rec = (unsigned long long)(d + 3);
         unsigned long long b0 = 0;
-        if (lane == 0) b0 = atomicAdd(&c->pool_used, rec * (unsigned long long)__popcll(rmask));
+        if (lane == 0)
+            b0 = atomicAdd(pool_lds ? pool_lds : &c->pool_used, rec * (unsigned long long)__popcll(rmask));
         b0 = __shfl(b0, 0, 64);
         off = b0 + rec * (unsigned long long)__popcll(rmask & lt);
     }
@@ -1242,8 +1255,9 @@ BNS_INLINE void apply_one(const DepthArgs &A, Ctl *c, int d, bool valid, const E
 BNS_INLINE void apply_edges(const DepthArgs &A, Ctl *c, int d, unsigned long long first,
                             unsigned long long stride, unsigned long long &req,
                             unsigned long long &rem, const Binom &bn, const ProbDev *probs,
-                            uint64_t *lds_bits = nullptr) {
-    const unsigned long long E = c->n_edges;
+                            uint64_t *lds_bits = nullptr, unsigned long long *pool_lds = nullptr,
+                            unsigned long long E = ~0ull) {
+    if (E == ~0ull) E = c->n_edges;
     const int lane = threadIdx.x & 63;
     // two strides per trip: both edges' loads are in flight together
     for (unsigned long long base = first; base < E; base += 2 * stride) {
@@ -1261,8 +1275,8 @@ BNS_INLINE void apply_edges(const DepthArgs &A, Ctl *c, int d, unsigned long lon
         }
         if (v0) req += (ma0 == ~0ull) ? r0.n : ma0 + 1;
         if (v1) req += (ma1 == ~0ull) ? r1.n : ma1 + 1;
-        apply_one(A, c, d, v0, r0, ma0, rem, bn, probs, lds_bits);
-        if (base + stride < E) apply_one(A, c, d, v1, r1, ma1, rem, bn, probs, lds_bits);
+        apply_one(A, c, d, v0, r0, ma0, rem, bn, probs, lds_bits, pool_lds);
+        if (base + stride < E) apply_one(A, c, d, v1, r1, ma1, rem, bn, probs, lds_bits, pool_lds);
     }
 }
 
@@ -1326,15 +1340,28 @@ __global__ __launch_bounds__(kWG) void k_apply(DepthArgs A) {
 __global__ __launch_bounds__(kSmallThreads) void k_apply_small(DepthArgs A) {
     __shared__ SmallSh sh;
     Ctl *c = A.ctl;
-    if (c->done) return;
-    const int d = c->depth;
-    const int w = threadIdx.x >> 6;
+    // One round of loads: control-block header, bit rows, problem records
+    // and the depth's binomial slice (staged by the preparation).
+    if (threadIdx.x == 0) {
+        sh.h_done = c->done;
+        sh.h_depth = c->depth;
+        sh.h_maxdeg = c->maxdeg;
+        sh.h_bstride = c->bstride;
+        sh.h_brows = c->brows;
+        sh.h_edges = c->n_edges;
+        sh.pool_ctr = c->pool_used;
+    }
     small_load(A, sh);
-    const Binom bn = stage_binom(A, c->maxdeg, d, sh.btab, kApplyBinom, kSmallThreads);
+    for (int i = threadIdx.x; i < kBinomLds; i += kSmallThreads) sh.btab[i] = c->bslice[i];
     __syncthreads();
+    if (sh.h_done) return;
+    const int d = sh.h_depth;
+    const int w = threadIdx.x >> 6;
+    const Binom bn = sh.h_bstride > 0 ? Binom{sh.btab, sh.h_bstride, sh.h_brows}
+                                      : Binom{A.binom, kBinomK, A.binom_rows};
     unsigned long long req = 0, rem = 0;
     apply_edges(A, c, d, (unsigned long long)w * 64, (unsigned long long)kSmallThreads, req, rem,
-                bn, A.n_probs <= kSmallProbs ? sh.probs : A.probs, sh.bits);
+                bn, A.n_probs <= kSmallProbs ? sh.probs : A.probs, sh.bits, &sh.pool_ctr, sh.h_edges);
     req = wave_sum(req);
     rem = wave_sum(rem);
     if ((threadIdx.x & 63) == 0) {
@@ -1348,16 +1375,35 @@ __global__ __launch_bounds__(kSmallThreads) void k_apply_small(DepthArgs A) {
             a += sh.red[0][i];
             b += sh.red[1][i];
         }
+        // (this kernel is the depth's only writer of these: plain stores)
         if (d < kMaxDepths) {
-            c->stats[d].required += a;
-            c->stats[d].removed += b;
+            c->stats[d].required = a;
+            c->stats[d].removed = b;
         }
+        c->pool_used = sh.pool_ctr;
         c->depth = d + 1;
     }
-    __syncthreads();
     // the bit rows after the removals, for the next depth's removal kernel
     for (int i = threadIdx.x; i < A.bit_words; i += kSmallThreads) A.adjbits[i] = sh.bits[i];
     prepare_block(A, c, d + 1, sh);
+}
+
+// Copies the control block and, with h_res, the removal depths and the
+// removal records written so far (at most res_pool_words) into pinned host
+// memory, so that the host reads a launch's results with no copy of its own.
+__global__ __launch_bounds__(kWG) void k_publish(DepthArgs A) {
+    const int64_t tid = (int64_t)blockIdx.x * kWG + threadIdx.x, nth = (int64_t)gridDim.x * kWG;
+    static_assert(sizeof(Ctl) % 16 == 0, "16-byte copies of the control block");
+    const uint4 *cs = reinterpret_cast<const uint4 *>(A.ctl);
+    uint4 *cd = reinterpret_cast<uint4 *>(A.h_ctl);
+    for (int64_t i = tid; i < (int64_t)(sizeof(Ctl) / 16); i += nth) cd[i] = cs[i];
+    if (!A.h_res) return;
+    const uint2 *rs = reinterpret_cast<const uint2 *>(A.rdepth);
+    uint2 *rd = reinterpret_cast<uint2 *>(A.h_res);
+    for (int64_t i = tid; i < A.res_rbytes / 8; i += nth) rd[i] = rs[i];
+    const int64_t used = min((int64_t)A.ctl->pool_used, A.res_pool_words);
+    int32_t *pd = reinterpret_cast<int32_t *>(A.h_res + A.res_rbytes);
+    for (int64_t i = tid; i < used; i += nth) pd[i] = A.pool[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -1372,6 +1418,13 @@ static int grid_rows(int n_globals) { return (n_globals + kWaves - 1) / kWaves; 
 hipError_t launch_init_search(const DepthArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_init_search, dim3(64, a.n_probs), dim3(kWG), 0, s, a);
     if (small_search(a)) hipLaunchKernelGGL(k_prepare_small, dim3(1), dim3(kSmallThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_publish(const DepthArgs &a, hipStream_t s) {
+    const int64_t words = std::max<int64_t>(a.h_res ? a.res_rbytes / 8 : 0, (int64_t)(sizeof(Ctl) / 16));
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(64, (words + kWG - 1) / kWG));
+    hipLaunchKernelGGL(k_publish, dim3(grid), dim3(kWG), 0, s, a);
     return hipGetLastError();
 }
 
