@@ -101,7 +101,12 @@ typedef struct bns_options {
                               (summed before G^2); a power of two in [1, 64]; 0 = default */
     int32_t tickets_per_grab; /* batched form: tests taken per grab of the shared ticket
                               counter, in [1, 8]; 0 = automatic */
-    int32_t reserved[3];   /* must be zero */
+    int32_t ticket_runs;   /* batched form: tickets dealt to the test kernel's grab
+                              counters one at a time (1) or in runs of 64 consecutive
+                              tickets (2: edges that share a column run on one XCD);
+                              0 = automatic (runs when the search's columns exceed
+                              64 MiB) */
+    int32_t reserved[2];   /* must be zero */
     void *stream;          /* hipStream_t; NULL = default stream */
 } bns_options;
 

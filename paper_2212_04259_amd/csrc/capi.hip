@@ -86,7 +86,9 @@ static bns_status read_options(const bns_options *in, bns_options *out) {
         return fail(BNS_E_INVALID_ARG, "options.max_replicas must be 0 or a power of two up to 64");
     if (out->tickets_per_grab < 0 || out->tickets_per_grab > kSlotsPerWave)
         return fail(BNS_E_INVALID_ARG, "options.tickets_per_grab must be in [0, %d]", kSlotsPerWave);
-    for (int i = 0; i < 3; ++i)
+    if (out->ticket_runs < 0 || out->ticket_runs > 2)
+        return fail(BNS_E_INVALID_ARG, "options.ticket_runs must be 0, 1 or 2");
+    for (int i = 0; i < 2; ++i)
         if (out->reserved[i] != 0) return fail(BNS_E_INVALID_ARG, "options.reserved must be zero");
     return BNS_OK;
 }
@@ -734,7 +736,8 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     // Columns beyond a quarter of the last-level cache: deal the tickets to
     // the grab counters in runs of 64 (edges that share a column run on one
     // XCD); else one at a time.
-    a.grab_block_log2 = col_bytes > kGrabRunBytes ? kGrabRunLog2 : 0;
+    const bool runs = o.ticket_runs == 2 || (o.ticket_runs == 0 && col_bytes > kGrabRunBytes);
+    a.grab_block_log2 = runs ? kGrabRunLog2 : 0;
 
     const int lds_bytes = tile.lds_words * 4;
     int wg = o.wg_per_cu ? o.wg_per_cu : depth_tests_max_wg_per_cu(lds_bytes);

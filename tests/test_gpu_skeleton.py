@@ -68,12 +68,40 @@ def test_plain_matches_golden(bns, k):
     dict(test_group=1, split_min_samples=2048, units_per_group=4, precision=1),
     dict(max_replicas=1), dict(max_replicas=16, tickets_per_grab=8),
     dict(test_group=1, max_replicas=4, tickets_per_grab=1),
+    dict(ticket_runs=1), dict(ticket_runs=2), dict(ticket_runs=2, test_group=1, tickets_per_grab=8),
+    dict(ticket_runs=2, split_min_samples=1024, units_per_group=16),
 ])
 def test_tile_shapes_and_modes_identical(bns, opts):
     g = load_golden(2)["datasets"][0]
     ds = _cfg(2)[0]
     got = _run(bns, ds, "cfg2", **opts)
     compare_skeleton(got, g, f"cfg2 {opts}")
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_ticket_runs_match_golden(bns, k):
+    # Tickets dealt to the grab counters in runs of 64 (the kernel instance
+    # that large searches use) on small workloads.
+    g = load_golden(k)["datasets"][0]
+    got = _run(bns, _cfg(k)[0], f"cfg{k} runs", ticket_runs=2)
+    compare_skeleton(got, g, f"cfg{k} ticket_runs=2")
+
+
+def test_large_search_results_copy_path(bns, orc):
+    # 2,000 variables: the multi-workgroup preparation and removal kernels,
+    # and results beyond what the last kernel publishes into host memory
+    # (4 MB of removal depths, more removal records than the published
+    # prefix), which are copied after the search.
+    ds = make_dataset(2000, 2600, 3, 2, 3, 0.5, 400, seed=777, alpha=0.01)
+    ref = orc.pc_skeleton(ds.data, ds.cards, ds.alpha, 1)
+    for runs in (1, 2):
+        print(f"skeleton n=2000 m=400 max_depth=1 ticket_runs={runs}", flush=True)
+        o = bns.bns_options_default(ticket_runs=runs)
+        got = bns.bns_pc_skeleton(ds.data, ds.cards, ds.alpha, 1, o)
+        assert np.array_equal(got.adj, ref.adj)
+        assert np.array_equal(got.depth, ref.depth)
+        assert got.sepsets == ref.sepsets
+        assert [s["tests_required"] for s in got.stats] == ref.tests
 
 
 def test_split_tables_stay_clean_across_searches(bns):
@@ -105,7 +133,7 @@ def test_cfg5_batch_of_64(bns):
     handles = [bns.bns_dataset_create(d.data, d.cards) for d in dss]
     # default options, then chunks shorter than most datasets' sample counts
     # (ragged chunk counts per test within one depth)
-    for opts in (dict(), dict(split_min_samples=3072, units_per_group=16)):
+    for opts in (dict(), dict(split_min_samples=3072, units_per_group=16), dict(ticket_runs=1)):
         print(f"  options {opts}", flush=True)
         o = bns.bns_options_default(**opts)
         outs = bns.bns_pc_skeleton_batch(handles, [d.alpha for d in dss],
