@@ -375,8 +375,10 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
         c->split_cap = cap;
         c->total_units = any_bad ? 0ull : total * C;
         // Grabs of several units amortise the decode latency when there is
-        // work for several rounds.
-        const unsigned long long per = total * C / (4ull * groups);
+        // work for many rounds; a group holds its batch, so larger batches
+        // also run more tests before earlier ranks of their edges finish
+        // (speculation): one unit per grab per eight rounds of all groups.
+        const unsigned long long per = total * C / (8ull * groups);
         c->batch = A.grab_fixed > 0 ? A.grab_fixed
                                     : (int)max(1ull, min(per, (unsigned long long)kSlotsPerWave));
         if (done_lds) *done_lds = (total == 0 || any_bad) ? 1 : 0;
