@@ -42,18 +42,24 @@ struct Binom {
 
 // Serial lexicographic unranking (one lane): positions of the rank-rr size-d
 // subset of {0..p-1}.
+// S(x) = number of subsets (with the current prefix) whose k-th element is < x
+//      = C(p - x0, j + 1) - C(p - x, j + 1)   (hockey-stick identity)
+// is non-decreasing in x, so the k-th element, the largest x in
+// [x0, p - j - 1] with S(x) <= rr, is found by bisection.
 __device__ inline void unrank_serial(const Binom &B, int64_t p, int d, uint64_t rr, int32_t *c) {
     int64_t x0 = 0;
     for (int k = 0; k < d; ++k) {
         const int j = d - k - 1;
         const uint64_t base = B.at(p - x0, j + 1);
-        int64_t x = x0;
-        // S(x) = number of subsets (with the current prefix) whose k-th element is < x
-        //      = C(p - x0, j + 1) - C(p - x, j + 1)   (hockey-stick identity)
-        while (x + 1 <= p - j - 1 && base - B.at(p - (x + 1), j + 1) <= rr) ++x;
-        c[k] = (int32_t)x;
-        rr -= base - B.at(p - x, j + 1);
-        x0 = x + 1;
+        int64_t lo = x0, hi = p - j - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (base - B.at(p - mid, j + 1) <= rr) lo = mid;
+            else hi = mid - 1;
+        }
+        c[k] = (int32_t)lo;
+        rr -= base - B.at(p - lo, j + 1);
+        x0 = lo + 1;
     }
 }
 
@@ -760,11 +766,16 @@ BNS_INLINE void unrank_lane(const uint64_t *tab, int stride, int rows, int64_t p
     for (int k = 0; k < d; ++k) {
         const int j = d - k - 1;
         const uint64_t base = bnm(tab, stride, rows, p - x0, j + 1);
-        int64_t x = x0;
-        while (x + 1 <= p - j - 1 && base - bnm(tab, stride, rows, p - (x + 1), j + 1) <= rr) ++x;
-        out[k] = (uint16_t)x;
-        rr -= base - bnm(tab, stride, rows, p - x, j + 1);
-        x0 = x + 1;
+        // largest x in [x0, p - j - 1] with S(x) <= rr, by bisection
+        int64_t lo = x0, hi = p - j - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (base - bnm(tab, stride, rows, p - mid, j + 1) <= rr) lo = mid;
+            else hi = mid - 1;
+        }
+        out[k] = (uint16_t)lo;
+        rr -= base - bnm(tab, stride, rows, p - lo, j + 1);
+        x0 = lo + 1;
     }
 }
 
