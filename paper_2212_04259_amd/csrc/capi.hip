@@ -153,6 +153,11 @@ struct DevCtx {
     DevBuf ci_tests, ci_z, ci_out, ci_tab, ci_taboff, plain_part, plain_ws, plain_out;
     CiOutDev *h_out = nullptr;  // pinned readback slot
     Ctl *h_ctl = nullptr;       // pinned control-block readback
+    // launch completion: the publishing kernel counts launches in pub (device:
+    // sequence, workgroup counter) and writes the count into h_flag (pinned)
+    unsigned long long *h_flag = nullptr;
+    void *pub = nullptr;
+    unsigned long long pub_expected = 0;
     void *hpin = nullptr;       // pinned staging for uploads and result downloads
     size_t hpin_bytes = 0;
     hipError_t pinned(size_t n) {
@@ -208,6 +213,10 @@ static bns_status get_ctx(int device, DevCtx **out) {
     HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     HIP_TRY(hipHostMalloc((void **)&c->h_out, sizeof(CiOutDev), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void **)&c->h_ctl, sizeof(Ctl), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void **)&c->h_flag, 64, hipHostMallocDefault));
+    *c->h_flag = 0;
+    HIP_TRY(hipMalloc(&c->pub, 64));
+    HIP_TRY(hipMemset(c->pub, 0, 64));
     *out = c.get();
     g_ctx.push_back(std::move(c));
     return BNS_OK;
@@ -605,14 +614,23 @@ static bns_status depth_graph(DevCtx &dc, const DepthArgs &a, int grid, int K, b
     return BNS_OK;
 }
 
-// Waits for the stream: polls it for up to 2 ms (a blocking wait wakes up
-// some microseconds late, which short launches notice), then blocks.
-static hipError_t wait_stream(hipStream_t s) {
+// Waits for a launch's results: polls the completion flag that its last
+// kernel writes into pinned memory (the stream itself reports completion
+// ~14 us after that kernel ends), checking the stream now and then for
+// errors; after 2 ms it blocks on the stream instead.  A stream that went
+// idle without raising the flag is an internal error.
+static hipError_t wait_published(hipStream_t s, const volatile unsigned long long *flag,
+                                 unsigned long long want) {
     const auto t0 = std::chrono::steady_clock::now();
-    for (;;) {
-        const hipError_t e = hipStreamQuery(s);
-        if (e != hipErrorNotReady) return e;
-        if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(2000)) return hipStreamSynchronize(s);
+    for (unsigned it = 1;; ++it) {
+        if (*flag == want) return hipSuccess;
+        if ((it & 63u) != 0u) continue;
+        hipError_t e = hipStreamQuery(s);
+        if (e == hipErrorNotReady && std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(2000))
+            e = hipStreamSynchronize(s);
+        if (e == hipErrorNotReady) continue;
+        if (e != hipSuccess) return e;
+        return *flag == want ? hipSuccess : hipErrorUnknown;
     }
 }
 
@@ -811,6 +829,9 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
         a.h_res = spec ? (char *)dc.hres : nullptr;
         a.res_rbytes = (int64_t)rbytes;
         a.res_pool_words = (int64_t)spec_pool;
+        a.pub_seq = (unsigned long long *)dc.pub;
+        a.pub_cnt = (unsigned int *)((char *)dc.pub + 8);
+        a.h_flag = dc.h_flag;
         if (use_graph) {
             st = depth_graph(dc, a, grid, K, d == 0, s, &ge);
             if (st != BNS_OK) return st;
@@ -825,7 +846,16 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
             }
             HIP_TRY(launch_publish(a, s));
         }
-        HIP_TRY(wait_stream(s));
+        {
+            const hipError_t we = wait_published(s, dc.h_flag, ++dc.pub_expected);
+            if (we != hipSuccess) {
+                // re-synchronise the expected count with the device's
+                unsigned long long v = 0;
+                if (hipStreamSynchronize(s) == hipSuccess && hipMemcpy(&v, dc.pub, sizeof(v), hipMemcpyDeviceToHost) == hipSuccess)
+                    dc.pub_expected = v;
+                HIP_TRY(we);
+            }
+        }
         const Ctl &c = *dc.h_ctl;
         if (c.error) {
             dc.split_dirty = true;  // a depth may have stopped with partial merge tables

@@ -56,6 +56,11 @@ struct DepthArgs {
     char *h_res;              // null, or removal depths (res_rbytes) then the first removal records
     int64_t res_rbytes;       // adjacency bytes rounded up to 8 (rdepth holds at least this many)
     int64_t res_pool_words;   // removal-record words copied at most
+    // Completion flag: the last workgroup of the publishing kernel, after all
+    // copies are visible to the host, writes ++*pub_seq into *h_flag.
+    unsigned long long *pub_seq;  // device: launches published so far
+    unsigned int *pub_cnt;        // device: workgroups of the current publish done (0 between)
+    unsigned long long *h_flag;   // pinned host
 };
 
 // Small searches keep the adjacency as bit rows in LDS and prepare each depth

@@ -1403,20 +1403,37 @@ __global__ __launch_bounds__(kSmallThreads) void k_apply_small(DepthArgs A) {
 
 // Copies the control block and, with h_res, the removal depths and the
 // removal records written so far (at most res_pool_words) into pinned host
-// memory, so that the host reads a launch's results with no copy of its own.
+// memory, so that the host reads a launch's results with no copy of its own;
+// then raises the completion flag, which the host sees earlier than the
+// stream's own completion.
 __global__ __launch_bounds__(kWG) void k_publish(DepthArgs A) {
     const int64_t tid = (int64_t)blockIdx.x * kWG + threadIdx.x, nth = (int64_t)gridDim.x * kWG;
     static_assert(sizeof(Ctl) % 16 == 0, "16-byte copies of the control block");
     const uint4 *cs = reinterpret_cast<const uint4 *>(A.ctl);
     uint4 *cd = reinterpret_cast<uint4 *>(A.h_ctl);
     for (int64_t i = tid; i < (int64_t)(sizeof(Ctl) / 16); i += nth) cd[i] = cs[i];
-    if (!A.h_res) return;
-    const uint2 *rs = reinterpret_cast<const uint2 *>(A.rdepth);
-    uint2 *rd = reinterpret_cast<uint2 *>(A.h_res);
-    for (int64_t i = tid; i < A.res_rbytes / 8; i += nth) rd[i] = rs[i];
-    const int64_t used = min((int64_t)A.ctl->pool_used, A.res_pool_words);
-    int32_t *pd = reinterpret_cast<int32_t *>(A.h_res + A.res_rbytes);
-    for (int64_t i = tid; i < used; i += nth) pd[i] = A.pool[i];
+    if (A.h_res) {
+        const uint2 *rs = reinterpret_cast<const uint2 *>(A.rdepth);
+        uint2 *rd = reinterpret_cast<uint2 *>(A.h_res);
+        for (int64_t i = tid; i < A.res_rbytes / 8; i += nth) rd[i] = rs[i];
+        const int64_t used = min((int64_t)A.ctl->pool_used, A.res_pool_words);
+        int32_t *pd = reinterpret_cast<int32_t *>(A.h_res + A.res_rbytes);
+        for (int64_t i = tid; i < used; i += nth) pd[i] = A.pool[i];
+    }
+    // every wave's copies visible to the host before its workgroup counts
+    // itself done; the last workgroup then writes the flag
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned int prev = atomicAdd(A.pub_cnt, 1u);
+        if (prev + 1u == gridDim.x) {
+            __threadfence_system();
+            *A.pub_cnt = 0u;
+            const unsigned long long v = *A.pub_seq + 1ull;
+            *A.pub_seq = v;
+            __hip_atomic_store(A.h_flag, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
