@@ -916,16 +916,16 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
         const int n = ds[k]->n;
         const int64_t base = probs[k].adj_off, nn = (int64_t)n * n;
         sk->n = n;
-        sk->adj.assign((size_t)nn, 0);
-        sk->depth.assign((size_t)nn, -1);
+        sk->adj.resize((size_t)nn);
+        sk->depth.resize((size_t)nn);
         sk->sepoff.assign((size_t)nn, -1);
-        for (int64_t e = 0; e < nn; ++e) {
-            const int8_t dd = hdep[base + e];
-            sk->depth[e] = dd;
-            const int64_t i = e / n, j = e - i * n;
-            sk->adj[e] = (dd < 0 && i != j) ? 1 : 0;
-            if (dd == 0) sk->sepoff[e] = 0;  // empty set
-        }
+        for (int64_t i = 0, e = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j, ++e) {
+                const int8_t dd = hdep[base + e];
+                sk->depth[e] = dd;
+                sk->adj[e] = (dd < 0 && i != j) ? 1 : 0;
+                if (dd == 0) sk->sepoff[e] = 0;  // empty set
+            }
         sk->stats = stats;
     }
     for (unsigned long long q = 0; q < pool_used;) {
