@@ -99,7 +99,7 @@ typedef struct bns_options {
                               1 = one wave (64 lanes), 2 = one workgroup (256 lanes) */
     int32_t max_replicas;  /* copies of a contingency table in LDS that lanes increment
                               (summed before G^2); a power of two in [1, 64]; 0 = default */
-    int32_t tickets_per_grab; /* batched form: tests taken per grab of the shared ticket
+    int32_t tickets_per_grab; /* batched form: tests a group takes per grab of a ticket
                               counter, in [1, 8]; 0 = automatic */
     int32_t ticket_runs;   /* batched form: tickets dealt to the test kernel's grab
                               counters one at a time (1) or in runs of 64 consecutive
@@ -213,7 +213,7 @@ bns_status bns_pc_skeleton_batch(const bns_dataset *const *ds, int32_t n_problem
  * shape of the per-depth test kernel: lanes per test, LDS budget and table
  * replication, tests per grab) by timing complete trial searches, one option
  * at a time from the defaults, each candidate measured `trials` times
- * (median; 0 = 3).  *best receives base with the fastest choices filled in
+ * (median; 0 = 5).  *best receives base with the fastest choices filled in
  * (base NULL = defaults).  The choice is cached per device and workload
  * (problem sizes, alphas, max depths), so repeated calls return at once.
  * The trial searches run on the device like bns_pc_skeleton_batch. */

@@ -1144,7 +1144,7 @@ extern "C" bns_status bns_autotune(const bns_dataset *const *ds, int32_t n_probl
     if (o.form != BNS_FORM_BATCHED) return fail(BNS_E_INVALID_ARG, "autotuning applies to the batched form");
     for (int32_t k = 0; k < n_problems; ++k)
         if (!ds[k]) return fail(BNS_E_INVALID_ARG, "dataset %d is NULL", k);
-    const int reps = trials ? trials : 3;
+    const int reps = trials ? trials : 5;
     // workload key: sizes, alphas (bits), depths, precision
     std::vector<int64_t> key;
     key.push_back(o.precision);
