@@ -731,8 +731,21 @@ BNS_INLINE double table_pass(const Grp &g, TestSh &t, const Plan &P, uint32_t *l
         uint32_t *cols = rows + P.rx * Zc;
         uint32_t *strata = cols + P.ry * Zc;
         if (src.gsrc) {
+            // eight device loads in flight per lane before any is stored
             const uint32_t *gs = src.gsrc + P.rxy * z0;
-            for (uint32_t i = g.rank; i < Tc; i += g.size) red[i] = load_device(gs + i);
+            for (uint32_t i0 = g.rank; i0 < Tc; i0 += 8u * (uint32_t)g.size) {
+                uint32_t v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const uint32_t i = i0 + (uint32_t)u * (uint32_t)g.size;
+                    v[u] = i < Tc ? load_device(gs + i) : 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const uint32_t i = i0 + (uint32_t)u * (uint32_t)g.size;
+                    if (i < Tc) red[i] = v[u];
+                }
+            }
             g.sync();
         } else {
             for (uint32_t i = g.rank; i < head; i += g.size) rep_tab[i] = 0u;
