@@ -132,7 +132,7 @@ def main():
                     help="run one device copy of this many MiB first (profiler byte calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build has no "
+        print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}): the library has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
