@@ -170,7 +170,7 @@ def main():
         # launch options chosen by the library's autotuner (untimed setup)
         opt = bns.bns_autotune(handles, alphas, maxd, opt)
         tuned = {f: getattr(opt, f) for f in ("test_group", "max_replicas", "lds_bytes",
-                                               "tickets_per_grab")}
+                                               "tickets_per_grab", "wave_depths", "block_depths")}
         knobs.update(tuned)
 
     def step(o):

@@ -106,6 +106,9 @@ typedef struct bns_options {
                               tickets (2: edges that share a column run on one XCD);
                               0 = automatic (runs when the search's columns exceed
                               64 MiB) */
+    uint32_t wave_depths;  /* batched form: per-depth override of test_group for depths
+                              d < 32: bit (1u << d) set = one wave per test at depth d */
+    uint32_t block_depths; /* same, one workgroup per test; no bit may be set in both */
     int32_t reserved[2];   /* must be zero */
     void *stream;          /* hipStream_t; NULL = default stream */
 } bns_options;
@@ -213,8 +216,11 @@ bns_status bns_pc_skeleton_batch(const bns_dataset *const *ds, int32_t n_problem
  * shape of the per-depth test kernel: lanes per test, LDS budget and table
  * replication, tests per grab) by timing complete trial searches, one option
  * at a time from the defaults, each candidate measured `trials` times
- * (median; 0 = 5).  *best receives base with the fastest choices filled in
- * (base NULL = defaults).  The choice is cached per device and workload
+ * (median; 0 = 5); then, unless base fixes the lanes per test, a choice per
+ * depth (wave_depths / block_depths) from the depth spans of trial searches
+ * with one wave and with one workgroup per test, kept if the whole search is
+ * faster.  *best receives base with the fastest choices filled in (base NULL =
+ * defaults).  The choice is cached per device and workload
  * (problem sizes, alphas, max depths), so repeated calls return at once.
  * The trial searches run on the device like bns_pc_skeleton_batch. */
 bns_status bns_autotune(const bns_dataset *const *ds, int32_t n_problems, const double *alpha,

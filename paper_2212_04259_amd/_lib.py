@@ -48,7 +48,8 @@ class bns_options(ctypes.Structure):
                 ("timing", ctypes.c_int32), ("split_min_samples", ctypes.c_int32),
                 ("units_per_group", ctypes.c_int32), ("test_group", ctypes.c_int32),
                 ("max_replicas", ctypes.c_int32), ("tickets_per_grab", ctypes.c_int32),
-                ("ticket_runs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
+                ("ticket_runs", ctypes.c_int32), ("wave_depths", ctypes.c_uint32),
+                ("block_depths", ctypes.c_uint32), ("reserved", ctypes.c_int32 * 2),
                 ("stream", ctypes.c_void_p)]
 
 

@@ -88,6 +88,8 @@ static bns_status read_options(const bns_options *in, bns_options *out) {
         return fail(BNS_E_INVALID_ARG, "options.tickets_per_grab must be in [0, %d]", kSlotsPerWave);
     if (out->ticket_runs < 0 || out->ticket_runs > 2)
         return fail(BNS_E_INVALID_ARG, "options.ticket_runs must be 0, 1 or 2");
+    if ((out->wave_depths & out->block_depths) != 0u)
+        return fail(BNS_E_INVALID_ARG, "options.wave_depths and options.block_depths share a depth");
     for (int i = 0; i < 2; ++i)
         if (out->reserved[i] != 0) return fail(BNS_E_INVALID_ARG, "options.reserved must be zero");
     return BNS_OK;
@@ -750,6 +752,8 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     a.split_min = o.split_min_samples == 0 ? kSplitMinDefault : o.split_min_samples;
     a.units_per_group = o.units_per_group == 0 ? kUnitsPerGroupDefault : o.units_per_group;
     a.mode_policy = o.test_group;
+    a.wave_depths = o.wave_depths;
+    a.block_depths = o.block_depths;
     a.grab_fixed = o.tickets_per_grab;
     // Columns beyond a quarter of the last-level cache: deal the tickets to
     // the grab counters in runs of 64 (edges that share a column run on one
@@ -1202,6 +1206,48 @@ extern "C" bns_status bns_autotune(const bns_dataset *const *ds, int32_t n_probl
                 cur = c;
                 cur_t = t;
             }
+        }
+    }
+    // Then per depth: one wave or one workgroup per test, whichever ran that
+    // depth's test kernel in less time (device-clock spans).  The skeleton,
+    // and so each depth's edges and tests, is the same either way.
+    auto depth_spans = [&](const bns_options &c, std::vector<double> *med) -> bns_status {
+        std::vector<std::vector<double>> sp;
+        for (int r = 0; r < reps + 1; ++r) {
+            bns_status s2 = bns_pc_skeleton_batch(ds, n_problems, alpha, max_depth, &c, outs.data());
+            if (s2 == BNS_OK && r > 0) {
+                const std::vector<bns_depth_stats> &dst = outs[0]->stats;
+                if (sp.size() < dst.size()) sp.resize(dst.size());
+                for (size_t d = 0; d < dst.size(); ++d) sp[d].push_back(dst[d].span_seconds);
+            }
+            for (auto *h : outs) bns_skeleton_free(h);
+            if (s2 != BNS_OK) return s2;
+        }
+        med->clear();
+        for (std::vector<double> &v : sp) {
+            std::sort(v.begin(), v.end());
+            med->push_back(v.empty() ? 0.0 : v[v.size() / 2]);
+        }
+        return BNS_OK;
+    };
+    if (o.test_group == 0 && o.wave_depths == 0u && o.block_depths == 0u) {
+        bns_options cw = cur, cb = cur, cm = cur;
+        cw.test_group = 1;
+        cb.test_group = 2;
+        std::vector<double> sw, sb;
+        st = depth_spans(cw, &sw);
+        if (st != BNS_OK) return st;
+        st = depth_spans(cb, &sb);
+        if (st != BNS_OK) return st;
+        cm.test_group = 0;
+        for (size_t d = 0; d < std::min(sw.size(), sb.size()) && d < 32; ++d)
+            (sw[d] < sb[d] ? cm.wave_depths : cm.block_depths) |= 1u << d;
+        double t = 0.0;
+        st = timed(cm, &t);
+        if (st != BNS_OK) return st;
+        if (t < cur_t * 0.98) {
+            cur = cm;
+            cur_t = t;
         }
     }
     *best = cur;

@@ -50,6 +50,8 @@ struct DepthArgs {
     int32_t mode_policy;      // 0 automatic, 1 one test per wave, 2 one test per workgroup
     int32_t grab_fixed;       // tickets per grab (0: from the ticket count)
     int32_t grab_block_log2;  // test kernel: units dealt to a grab counter in runs of 2^this (0 or kGrabRunLog2)
+    uint32_t wave_depths;     // depths d < 32 with bit d set: one test per wave (overrides mode_policy)
+    uint32_t block_depths;    // same, one test per workgroup
     int32_t pad2;
     // Results of a launch, written into pinned host memory by its last kernel.
     Ctl *h_ctl;               // copy of the control block

@@ -347,9 +347,13 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
         // (4x the LDS and lanes per test: shorter tests, less speculation).
         // Automatic: a workgroup per test unless there are tickets for
         // several rounds of all waves.
+        // Per-depth overrides (depths below 32) come first.
         const unsigned long long tw = (unsigned long long)max(A.test_waves, 1);
-        const int mode = (A.mode_policy == 2) ? 1
-                       : (A.mode_policy == 1) ? 0
+        const uint32_t dbit = d < 32 ? 1u << d : 0u;
+        const int mode = (A.block_depths & dbit) ? 1
+                       : (A.wave_depths & dbit)  ? 0
+                       : (A.mode_policy == 2)    ? 1
+                       : (A.mode_policy == 1)    ? 0
                        : (total < kWaveModeRounds * tw ? 1 : 0);
         const unsigned long long groups = mode ? max(tw / kWaves, 1ull) : tw;
         // Fewer tickets than half the groups: cut each test's samples into

@@ -74,7 +74,8 @@ def test_bad_options_rejected(bns):
     for bad in (dict(split_min_samples=-2), dict(units_per_group=-1), dict(units_per_group=5000),
                 dict(test_group=3), dict(test_group=-1), dict(max_replicas=3),
                 dict(max_replicas=128), dict(tickets_per_grab=9), dict(tickets_per_grab=-1),
-                dict(ticket_runs=3), dict(ticket_runs=-1)):
+                dict(ticket_runs=3), dict(ticket_runs=-1),
+                dict(wave_depths=0b110, block_depths=0b011)):
         o = bns.bns_options_default(**bad)
         with pytest.raises(bns.BnsError, match="options"):
             bns.bns_pc_skeleton(np.zeros((3, 10), np.uint8), np.array([2, 2, 2], np.uint8),

@@ -87,6 +87,16 @@ def test_ticket_runs_match_golden(bns, k):
     compare_skeleton(got, g, f"cfg{k} ticket_runs=2")
 
 
+@pytest.mark.parametrize("k", [1, 2])
+def test_per_depth_groups_match_golden(bns, k):
+    # Lanes per test chosen per depth (wave at even depths, workgroup at odd
+    # ones, and the reverse) leave the skeleton and sepsets unchanged.
+    g = load_golden(k)["datasets"][0]
+    for wave, block in ((0x55555555, 0xAAAAAAAA), (0xAAAAAAAA, 0x55555555)):
+        got = _run(bns, _cfg(k)[0], f"cfg{k} depths {wave:#x}", wave_depths=wave, block_depths=block)
+        compare_skeleton(got, g, f"cfg{k} wave_depths={wave:#x}")
+
+
 def test_large_search_results_copy_path(bns, orc):
     # 2,000 variables: the multi-workgroup preparation and removal kernels,
     # and results beyond what the last kernel publishes into host memory
