@@ -123,6 +123,10 @@ def main():
     ap.add_argument("--test-group", type=int, default=0, help="0 auto, 1 wave, 2 workgroup")
     ap.add_argument("--max-replicas", type=int, default=0)
     ap.add_argument("--tickets-per-grab", type=int, default=0)
+    ap.add_argument("--wave-depths", type=int, default=0,
+                    help="bit d set: one wave per test at depth d")
+    ap.add_argument("--block-depths", type=int, default=0,
+                    help="bit d set: one workgroup per test at depth d")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
@@ -163,7 +167,8 @@ def main():
     knobs = dict(precision=a.precision, lds_bytes=a.lds_bytes, wg_per_cu=a.wg_per_cu,
                  split_min_samples=a.split_min, units_per_group=a.units_per_group,
                  test_group=a.test_group, max_replicas=a.max_replicas,
-                 tickets_per_grab=a.tickets_per_grab)
+                 tickets_per_grab=a.tickets_per_grab, wave_depths=a.wave_depths,
+                 block_depths=a.block_depths)
     opt = bns.bns_options_default(**knobs)
     tuned = None
     if not a.no_autotune:
