@@ -282,6 +282,11 @@ __global__ __launch_bounds__(kWG) void k_edges(DepthArgs A) {
 // ranks [2^L - 1, 2^(L+1) - 1) of the first level_cnt[L] edges, rank-major.
 // Tickets per test wave from which one test per wave beats one per workgroup.
 constexpr unsigned long long kWaveModeRounds = 6;
+// Below it, one test per wave also wins at depths up to kWaveModeSmallDepth
+// when every wave gets at most one ticket but a workgroup would take two or
+// more rounds: the longer single-wave test costs less than the extra rounds
+// of per-test latency, and tables of so few columns fit a wave's LDS share.
+constexpr int kWaveModeSmallDepth = 2;
 
 BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist, int d, int maxdeg,
                             unsigned int *cursor_lds = nullptr, int *done_lds = nullptr) {
@@ -346,7 +351,8 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
         // Group per test: a wave (no workgroup barriers), or a workgroup
         // (4x the LDS and lanes per test: shorter tests, less speculation).
         // Automatic: a workgroup per test unless there are tickets for
-        // several rounds of all waves.
+        // several rounds of all waves, or, at shallow depths, for a quarter
+        // to one round of them.
         // Per-depth overrides (depths below 32) come first.
         const unsigned long long tw = (unsigned long long)max(A.test_waves, 1);
         const uint32_t dbit = d < 32 ? 1u << d : 0u;
@@ -354,7 +360,9 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
                        : (A.wave_depths & dbit)  ? 0
                        : (A.mode_policy == 2)    ? 1
                        : (A.mode_policy == 1)    ? 0
-                       : (total < kWaveModeRounds * tw ? 1 : 0);
+                       : (total >= kWaveModeRounds * tw) ? 0
+                       : (d <= kWaveModeSmallDepth && 4ull * total >= tw && total <= tw) ? 0
+                       : 1;
         const unsigned long long groups = mode ? max(tw / kWaves, 1ull) : tw;
         // Fewer tickets than half the groups: cut each test's samples into
         // chunks of at least split_min samples, counted by different groups
