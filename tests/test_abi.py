@@ -39,6 +39,7 @@ def test_options_defaults(bns):
     assert o.precision == bns.BNS_PREC_FP32_RECHECK
     assert o.recheck_band == 1e-3
     assert o.use_graph == 1 and o.timing == 0
+    assert o.wave_depths == 0 and o.block_depths == 0 and list(o.reserved) == [0, 0]
 
 
 @pytest.mark.parametrize("data,cards,alpha,maxd,msg", [
