@@ -280,8 +280,11 @@ __global__ __launch_bounds__(kWG) void k_edges(DepthArgs A) {
 // One wave: ticket levels.  Edges are ordered by their number of levels,
 // descending, so the edges with a test of rank r form a prefix; level L holds
 // ranks [2^L - 1, 2^(L+1) - 1) of the first level_cnt[L] edges, rank-major.
-// Tickets per test wave from which one test per wave beats one per workgroup.
+// Tickets per test wave from which one test per wave beats one per workgroup
+// (twice as many from depth kWaveModeDeepDepth on: bigger tables cost a wave
+// more passes over its quarter of the LDS and a longer epilogue).
 constexpr unsigned long long kWaveModeRounds = 6;
+constexpr int kWaveModeDeepDepth = 3;
 // Below it, one test per wave also wins at depths up to kWaveModeSmallDepth
 // when every wave gets at most one ticket but a workgroup would take two or
 // more rounds: the longer single-wave test costs less than the extra rounds
@@ -351,8 +354,8 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
         // Group per test: a wave (no workgroup barriers), or a workgroup
         // (4x the LDS and lanes per test: shorter tests, less speculation).
         // Automatic: a workgroup per test unless there are tickets for
-        // several rounds of all waves, or, at shallow depths, for a quarter
-        // to one round of them.
+        // several rounds of all waves (more at deep depths), or, at shallow
+        // depths, for a quarter to one round of them.
         // Per-depth overrides (depths below 32) come first.
         const unsigned long long tw = (unsigned long long)max(A.test_waves, 1);
         const uint32_t dbit = d < 32 ? 1u << d : 0u;
@@ -360,7 +363,7 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
                        : (A.wave_depths & dbit)  ? 0
                        : (A.mode_policy == 2)    ? 1
                        : (A.mode_policy == 1)    ? 0
-                       : (total >= kWaveModeRounds * tw) ? 0
+                       : (total >= kWaveModeRounds * tw * (d >= kWaveModeDeepDepth ? 2ull : 1ull)) ? 0
                        : (d <= kWaveModeSmallDepth && 4ull * total >= tw && total <= tw) ? 0
                        : 1;
         const unsigned long long groups = mode ? max(tw / kWaves, 1ull) : tw;
