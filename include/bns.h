@@ -214,13 +214,14 @@ bns_status bns_pc_skeleton_batch(const bns_dataset *const *ds, int32_t n_problem
 
 /* Chooses launch options for the batched search of these datasets (the tile
  * shape of the per-depth test kernel: lanes per test, LDS budget and table
- * replication, tests per grab) by timing complete trial searches, one option
- * at a time from the defaults, each candidate measured `trials` times
- * (median; 0 = 5); then, unless base fixes the lanes per test, a choice per
- * depth (wave_depths / block_depths) from the depth spans of trial searches
- * with one wave and with one workgroup per test, kept if the whole search is
- * faster.  *best receives base with the fastest choices filled in (base NULL =
- * defaults).  The choice is cached per device and workload
+ * replication, tests per grab) by timing complete trial searches, each
+ * candidate measured `trials` times (median; 0 = 5).  Unless base fixes the
+ * lanes per test, they are first chosen per depth (wave_depths /
+ * block_depths) from the depth spans of trial searches with one wave and with
+ * one workgroup per test; then every combination of the other options that
+ * base leaves open (at most 27); then the per-depth choice again under them.
+ * Each choice is kept only if the whole search gets faster.  *best receives base with the fastest choices filled in
+ * (base NULL = defaults).  The choice is cached per device and workload
  * (problem sizes, alphas, max depths), so repeated calls return at once.
  * The trial searches run on the device like bns_pc_skeleton_batch. */
 bns_status bns_autotune(const bns_dataset *const *ds, int32_t n_problems, const double *alpha,

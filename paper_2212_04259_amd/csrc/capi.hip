@@ -1186,29 +1186,7 @@ extern "C" bns_status bns_autotune(const bns_dataset *const *ds, int32_t n_probl
     double cur_t = 0.0;
     st = timed(cur, &cur_t);
     if (st != BNS_OK) return st;
-    // one option at a time, keeping each improvement
-    const int32_t groups[] = {0, 1, 2};
-    const int32_t reps_opts[] = {0, 16, 64};
-    const int32_t lds_opts[] = {0, 32768, 49152};
-    const int32_t grab_opts[] = {0, 1, 2};
-    for (int knob = 0; knob < 4; ++knob) {
-        for (int v = 0; v < 3; ++v) {
-            bns_options c = cur;
-            if (knob == 0) { if (o.test_group) continue; c.test_group = groups[v]; }
-            if (knob == 1) { if (o.max_replicas) continue; c.max_replicas = reps_opts[v]; }
-            if (knob == 2) { if (o.lds_bytes) continue; c.lds_bytes = lds_opts[v]; }
-            if (knob == 3) { if (o.tickets_per_grab) continue; c.tickets_per_grab = grab_opts[v]; }
-            if (std::memcmp(&c, &cur, sizeof(c)) == 0) continue;
-            double t = 0.0;
-            st = timed(c, &t);
-            if (st != BNS_OK) return st;
-            if (t < cur_t * 0.98) {  // keep only clear gains
-                cur = c;
-                cur_t = t;
-            }
-        }
-    }
-    // Then per depth: one wave or one workgroup per test, whichever ran that
+    // Per depth: one wave or one workgroup per test, whichever ran that
     // depth's test kernel in less time (device-clock spans).  The skeleton,
     // and so each depth's edges and tests, is the same either way.
     auto depth_spans = [&](const bns_options &c, std::vector<double> *med) -> bns_status {
@@ -1230,26 +1208,67 @@ extern "C" bns_status bns_autotune(const bns_dataset *const *ds, int32_t n_probl
         }
         return BNS_OK;
     };
-    if (o.test_group == 0 && o.wave_depths == 0u && o.block_depths == 0u) {
+    // The per-depth choice under cur's other options, kept when the whole
+    // search gets faster.
+    auto try_depths = [&]() -> bns_status {
+        if (o.test_group != 0 || o.wave_depths != 0u || o.block_depths != 0u) return BNS_OK;
         bns_options cw = cur, cb = cur, cm = cur;
+        cw.wave_depths = cw.block_depths = cb.wave_depths = cb.block_depths = 0u;
         cw.test_group = 1;
         cb.test_group = 2;
         std::vector<double> sw, sb;
-        st = depth_spans(cw, &sw);
-        if (st != BNS_OK) return st;
-        st = depth_spans(cb, &sb);
-        if (st != BNS_OK) return st;
+        bns_status s2 = depth_spans(cw, &sw);
+        if (s2 != BNS_OK) return s2;
+        s2 = depth_spans(cb, &sb);
+        if (s2 != BNS_OK) return s2;
         cm.test_group = 0;
+        cm.wave_depths = cm.block_depths = 0u;
         for (size_t d = 0; d < std::min(sw.size(), sb.size()) && d < 32; ++d)
             (sw[d] < sb[d] ? cm.wave_depths : cm.block_depths) |= 1u << d;
+        if (std::memcmp(&cm, &cur, sizeof(cm)) == 0) return BNS_OK;
         double t = 0.0;
-        st = timed(cm, &t);
-        if (st != BNS_OK) return st;
-        if (t < cur_t * 0.98) {
+        s2 = timed(cm, &t);
+        if (s2 != BNS_OK) return s2;
+        if (t < cur_t * 0.99) {
             cur = cm;
             cur_t = t;
         }
+        return BNS_OK;
+    };
+    // Groups per depth first (they matter most); then every combination of
+    // replication cap, LDS budget and grab size that base leaves open (a grid
+    // of at most 27, so the result does not depend on the order of a greedy
+    // descent), keeping a combination only on a clear gain; then the groups
+    // per depth again under the chosen options.
+    st = try_depths();
+    if (st != BNS_OK) return st;
+    const int32_t reps_opts[] = {0, 16, 64};
+    const int32_t lds_opts[] = {0, 32768, 49152};
+    const int32_t grab_opts[] = {0, 1, 2};
+    const bns_options start = cur;
+    for (int ir = 0; ir < 3; ++ir) {
+        if (o.max_replicas && ir) break;
+        for (int il = 0; il < 3; ++il) {
+            if (o.lds_bytes && il) break;
+            for (int ig = 0; ig < 3; ++ig) {
+                if (o.tickets_per_grab && ig) break;
+                bns_options c = start;
+                if (!o.max_replicas) c.max_replicas = reps_opts[ir];
+                if (!o.lds_bytes) c.lds_bytes = lds_opts[il];
+                if (!o.tickets_per_grab) c.tickets_per_grab = grab_opts[ig];
+                if (std::memcmp(&c, &cur, sizeof(c)) == 0) continue;
+                double t = 0.0;
+                st = timed(c, &t);
+                if (st != BNS_OK) return st;
+                if (t < cur_t * 0.98) {  // keep only clear gains
+                    cur = c;
+                    cur_t = t;
+                }
+            }
+        }
     }
+    st = try_depths();
+    if (st != BNS_OK) return st;
     *best = cur;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune.push_back(TuneEntry{device, key, cur});
