@@ -731,17 +731,18 @@ BNS_INLINE double table_pass(const Grp &g, TestSh &t, const Plan &P, uint32_t *l
         uint32_t *cols = rows + P.rx * Zc;
         uint32_t *strata = cols + P.ry * Zc;
         if (src.gsrc) {
-            // eight device loads in flight per lane before any is stored
+            // sixteen device loads in flight per lane before any is stored
+            // (4,096 cells per round trip of a workgroup)
             const uint32_t *gs = src.gsrc + P.rxy * z0;
-            for (uint32_t i0 = g.rank; i0 < Tc; i0 += 8u * (uint32_t)g.size) {
-                uint32_t v[8];
+            for (uint32_t i0 = g.rank; i0 < Tc; i0 += 16u * (uint32_t)g.size) {
+                uint32_t v[16];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < 16; ++u) {
                     const uint32_t i = i0 + (uint32_t)u * (uint32_t)g.size;
                     v[u] = i < Tc ? load_device(gs + i) : 0u;
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < 16; ++u) {
                     const uint32_t i = i0 + (uint32_t)u * (uint32_t)g.size;
                     if (i < Tc) red[i] = v[u];
                 }
