@@ -762,11 +762,19 @@ BNS_INLINE double table_pass(const Grp &g, TestSh &t, const Plan &P, uint32_t *l
             }
         }
         if (src.gdst) {
+            // Adds in the returning form: once an add's old value has arrived
+            // the add has been performed at the device's coherence point, so
+            // the group's wait for its memory operations, before the chunk
+            // counter is incremented, orders every add of the chunk before the
+            // increment.  (The returned values are kept live; counts stay
+            // below 2^31, so their union is never all ones.)
             uint32_t *dst = src.gdst + P.rxy * z0;
+            uint32_t seen = 0u;
             for (uint32_t i = g.rank; i < Tc; i += g.size) {
                 const uint32_t v = red[i];
-                if (v) __hip_atomic_fetch_add(dst + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (v) seen |= __hip_atomic_fetch_add(dst + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
+            if (seen == ~0u) t.bcast_i[1] = 1;
             if (c + 1 < P.nchunks) g.sync();
             continue;
         }
