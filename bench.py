@@ -8,6 +8,9 @@ device memory.  The default workload is the 60-variable, 50,000-row network
 (the configuration the plain-versus-batched metric is quoted on).  Prints one
 JSON line; ``value`` is CI tests per second, counting the tests of the
 sequential order (per edge, up to and including its first accepting test).
+After timing, one of the timed searches is compared with the stored oracle
+results of the workload (skeleton, removal depths, sepsets, per-depth test
+counts); a mismatch sets ``parity`` false and the exit status to 1.
 """
 
 import argparse
@@ -21,15 +24,43 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TIMING_SEARCHES = 5
+# Integer vector ALU of MI355X: 256 compute units, 4 SIMDs of 16 lanes each
+# (a wave64 instruction occupies a SIMD for 4 cycles), 2.4 GHz peak clock.
+ALU_LANE_OPS_PER_S = 256 * 64 * 2.4e9
 
 
 def _sum(stats, key):
     return sum(s[key] for s in stats)
 
 
-def _stats_of(bns, h):
-    sk = bns.collect(h)
-    return sk, sk.stats
+def depth_totals(sks):
+    """Per-depth counters of a search over all its problems: each handle of a
+    multi-dataset search holds its own problem's counters (up to its last
+    depth with a test); the launch timings are shared."""
+    n = max(len(sk.stats) for sk in sks)
+    out = []
+    for d in range(n):
+        rows = [sk.stats[d] for sk in sks if d < len(sk.stats)]
+        t = {k: sum(r[k] for r in rows) for k in ("edges", "tests_required", "tests_executed", "removed",
+                                                   "rechecks", "tickets", "operand_bytes")}
+        t["depth"] = d
+        t["span_seconds"] = rows[0]["span_seconds"]
+        t["kernel_seconds"] = rows[0]["kernel_seconds"]
+        out.append(t)
+    return out
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
 
 
 def cpu_baseline(datasets, budget_s=10.0):
@@ -45,8 +76,10 @@ def cpu_baseline(datasets, budget_s=10.0):
         el = time.perf_counter() - t0
         if el >= budget_s or runs >= 50:
             break
+    model, avail = host_cpu()
     return dict(value=tests / el, unit="CI tests/s", cores=1, kind="oracle",
-                sample=f"{runs} full run(s) of the workload, single thread, {el:.1f} s")
+                sample=f"{runs} full run(s) of the workload, single thread, {el:.1f} s",
+                cpu_model=model, host_cpus_available=avail)
 
 
 def kernel_sources_sha256():
@@ -64,10 +97,11 @@ def kernel_sources_sha256():
 
 
 def measured_traffic(workload):
-    """HBM bytes per test launch from the committed rocprofv3 counter summary
-    of this workload (FETCH_SIZE + WRITE_SIZE, calibrated against a copy of
-    known size), or None when there is none or the kernels have changed
-    since the counters were taken."""
+    """Bytes per test launch that left L2 (rocprofv3 FETCH_SIZE + WRITE_SIZE,
+    calibrated against a copy of known size) from the committed counter
+    summary of this workload, or None when there is none or the kernels have
+    changed since the counters were taken.  FETCH_SIZE counts L2 misses,
+    which the Infinity Cache may still serve: an upper bound on DRAM bytes."""
     path = os.path.join(ROOT, "profiles", f"k_depth_tests_{workload}_counters.json")
     if not os.path.exists(path):
         return None
@@ -76,6 +110,25 @@ def measured_traffic(workload):
     if rec.get("kernel_sources_sha256") != kernel_sources_sha256():
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def streaming_read_peak_gbs(torch, gib=4, reps=10):
+    """Device read bandwidth of this machine: a reduction over a buffer far larger
+    than the last-level cache (GB/s, best of reps)."""
+    n = gib << 30
+    x = torch.ones(n // 4, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    best = 0.0
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s = torch.sum(x, dtype=torch.int64)
+        e1.record()
+        e1.synchronize()
+        best = max(best, n / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del s, x
+    torch.cuda.empty_cache()
+    return best
 
 
 def precision_report(bns, handle, ds, per_depth=2000, seed=7):
@@ -108,6 +161,45 @@ def precision_report(bns, handle, ds, per_depth=2000, seed=7):
     }
 
 
+def search_error_report(bns, handles, alphas, maxd, knobs):
+    """The search's own tests in verification mode (every executed test also
+    evaluated in FP64): FP32 relative error of G^2 per depth, untimed."""
+    o = bns.bns_options_default(report_errors=1, **knobs)
+    if len(handles) == 1:
+        sks = [bns.bns_pc_skeleton_dataset(handles[0], alphas[0], maxd[0], o)]
+    else:
+        sks = bns.bns_pc_skeleton_batch(handles, alphas, maxd, o)
+    per_depth = []
+    for d in range(max(len(sk.stats) for sk in sks)):
+        rows = [sk.stats[d] for sk in sks if d < len(sk.stats)]
+        per_depth.append({"depth": d, "tests": sum(r["err_tests"] for r in rows),
+                          "max": max(r["err_max"] for r in rows),
+                          "p99_max_over_problems": max(r["err_p99"] for r in rows),
+                          "p50_max_over_problems": max(r["err_p50"] for r in rows),
+                          "fp32_only_flips": sum(r["err_flips"] for r in rows),
+                          "rechecks": sum(r["rechecks"] for r in rows)})
+    return {"tests": sum(p["tests"] for p in per_depth),
+            "max": max(p["max"] for p in per_depth),
+            "fp32_only_flips": sum(p["fp32_only_flips"] for p in per_depth),
+            "per_depth": per_depth}
+
+
+def check_parity(sks, config):
+    """Compares a timed search's results with the stored oracle results of
+    the workload (tests/golden); returns (ok, message)."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from golden_util import compare_skeleton, load_golden
+    gold = load_golden(config)["datasets"]
+    if len(gold) != len(sks):
+        return False, f"{len(sks)} results against {len(gold)} stored"
+    try:
+        for i, (sk, g) in enumerate(zip(sks, gold)):
+            compare_skeleton(sk, g, f"dataset {i}")
+    except AssertionError as e:
+        return False, str(e)
+    return True, "identical to the oracle"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,9 +219,11 @@ def main():
                     help="bit d set: one wave per test at depth d")
     ap.add_argument("--block-depths", type=int, default=0,
                     help="bit d set: one workgroup per test at depth d")
+    ap.add_argument("--depth0", type=int, default=0, help="0 auto, 1 test kernel, 2 pair tables")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-stream-peak", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the given options instead of the autotuned ones")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -168,14 +262,15 @@ def main():
                  split_min_samples=a.split_min, units_per_group=a.units_per_group,
                  test_group=a.test_group, max_replicas=a.max_replicas,
                  tickets_per_grab=a.tickets_per_grab, wave_depths=a.wave_depths,
-                 block_depths=a.block_depths)
+                 block_depths=a.block_depths, depth0=a.depth0)
     opt = bns.bns_options_default(**knobs)
     tuned = None
     if not a.no_autotune:
         # launch options chosen by the library's autotuner (untimed setup)
         opt = bns.bns_autotune(handles, alphas, maxd, opt)
         tuned = {f: getattr(opt, f) for f in ("test_group", "max_replicas", "lds_bytes",
-                                               "tickets_per_grab", "wave_depths", "block_depths")}
+                                               "tickets_per_grab", "wave_depths", "block_depths",
+                                               "split_min_samples", "units_per_group", "depth0")}
         knobs.update(tuned)
 
     def step(o):
@@ -194,36 +289,57 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ms = 1e3 * el / a.steps
-    # test-kernel execution spans of the timed searches (device clock stamps)
-    span = 0.0
+    # test-kernel execution spans of the timed searches (device clock stamps,
+    # per depth), and the results of the first timed search for the parity check
+    spans = []
+    first = None
     for hs in kept:
-        sk0 = bns.collect(hs[0])
-        span += _sum(sk0.stats, "span_seconds")
-        for h in hs[1:]:
-            bns.free_skeleton(h)
-    span /= len(kept)
+        sks = [bns.collect(h) for h in hs]
+        if first is None:
+            first = sks
+        spans.append([t["span_seconds"] for t in depth_totals(sks)])
+    ndep = min(len(s) for s in spans)
+    span_d = [sum(s[d] for s in spans) / len(spans) for d in range(ndep)]
+    span = sum(span_d)
+    parity_ok, parity_msg = check_parity(first, a.config)
 
     # Counters of a few more (untimed) searches, with HIP events around each
-    # depth's persistent test launch (on the launch stream) for the roofline
-    # of that kernel; the kernel time is the mean over these searches.
+    # depth's persistent test launch (on the launch stream); the event time
+    # is the mean over these searches.
     topt = bns.bns_options_default(timing=1, **knobs)
     ksecs = []
     for _ in range(TIMING_SEARCHES):
-        hs = step(topt)
-        sks = [bns.collect(h) for h in hs]
-        ksecs.append(_sum(sks[0].stats, "kernel_seconds"))
-    stats = sks[0].stats          # a multi-dataset search shares one set of counters
-    required = _sum(stats, "tests_required")
-    executed = _sum(stats, "tests_executed")
-    rechecks = _sum(stats, "rechecks")
-    obytes = _sum(stats, "operand_bytes")
+        sks = [bns.collect(h) for h in step(topt)]
+        tot = depth_totals(sks)
+        ksecs.append(_sum(tot, "kernel_seconds"))
+    required = _sum(tot, "tests_required")
+    executed = _sum(tot, "tests_executed")
+    rechecks = _sum(tot, "rechecks")
+    obytes_exec = _sum(tot, "operand_bytes")
     ksec = sum(ksecs) / len(ksecs)
-    m_total = sum(d.n_samples for d in dss)
-    rows_per_test = m_total / len(dss)
-    launches = len(stats)
-    # achieved: operand bytes per launch over the launch's execution span in
-    # the timed searches
-    achieved = (obytes / launches) / (span / launches) / 1e9 if span > 0 else None
+    m_of = [d.n_samples for d in dss]
+    launches = len(tot)
+    # Algorithmic work of the method's own (required) tests: a depth-d test
+    # reads (d + 2) m operand bytes and does (d + 2) m int32 operations (d + 1
+    # cell-index multiply-adds and one table increment per sample).  Per-problem
+    # sample counts differ in a batch, so the required bytes come per problem.
+    req_bytes_d = [0.0] * launches
+    for sk, m in zip(first, m_of):
+        for d, s in enumerate(sk.stats):
+            req_bytes_d[d] += s["tests_required"] * (d + 2) * m
+    req_bytes = sum(req_bytes_d)
+    ops_rate = req_bytes / span if span > 0 else 0.0          # int32 ops/s (= required bytes/s)
+    traffic = measured_traffic(CONFIGS[a.config]["name"])
+    per_depth = []
+    for d in range(min(launches, ndep)):
+        sd = span_d[d]
+        per_depth.append({
+            "depth": d, "span_us": sd * 1e6, "tests_required": tot[d]["tests_required"],
+            "tests_executed": tot[d]["tests_executed"],
+            "alu_frac": (req_bytes_d[d] / sd) / ALU_LANE_OPS_PER_S if sd > 0 else None,
+            "operand_gbs_required": req_bytes_d[d] / sd / 1e9 if sd > 0 else None,
+        })
+    stream_peak = None if a.no_stream_peak else streaming_read_peak_gbs(torch)
 
     out = {
         "metric": "CI tests/sec (batched, same skeleton as the FP64 oracle)",
@@ -236,37 +352,62 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u8",
+        "dtype": "i32 counts + f32 G2 + f64 p",
         "data": "synthetic",
         "config": {
             "workload": CONFIGS[a.config]["name"],
             "datasets": len(dss),
             "n_vars": [d.n_vars for d in dss] if len(dss) > 1 else dss[0].n_vars,
-            "n_samples": m_total,
+            "n_samples": sum(m_of),
             "alpha": alphas[0],
             "max_depth": maxd[0],
             "g2_arithmetic": "fp64" if a.precision == 1 else "fp32 + fp64 recheck",
             "form": "batched persistent per-depth launch",
             "autotuned": tuned,
         },
+        "parity": parity_ok,
+        "parity_detail": parity_msg,
         "tests_required_per_step": required,
         "tests_executed_per_step": executed,
         "waste_ratio": executed / required - 1.0 if required else 0.0,
         "recheck_fraction": rechecks / executed if executed else 0.0,
-        "sample_rows_per_s": required * rows_per_test / (ms * 1e-3),
+        "sample_rows_per_s": sum(s["tests_required"] * m for sk, m in zip(first, m_of) for s in sk.stats)
+        / (ms * 1e-3),
         "depths": launches,
+        # The test kernel's binding roof class: its operands are cache-resident
+        # on this workload (DRAM traffic a few percent of the operand bytes),
+        # so the roof it would meet with its per-test latency hidden is the
+        # integer vector ALU of the counting loop.
         "roofline": {
-            "bound": "hbm",
+            "bound": "alu",
             "kernel": "k_depth_tests",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": measured_traffic(CONFIGS[a.config]["name"]),
+            "achieved": ops_rate / 1e12,
+            "peak": ALU_LANE_OPS_PER_S / 1e12,
+            "unit": "T int32 ops/s",
+            "frac": ops_rate / ALU_LANE_OPS_PER_S,
+            "traffic": traffic,
+            "basis": "(d+2) int32 ops per sample of each required depth-d test over the test "
+                     "kernel's device-clock span; peak 256 CU x 64 lanes x 2.4 GHz",
             "launches": launches,
             "kernel_ms_per_step": span * 1e3,
             "kernel_ms_per_step_hip_events": ksec * 1e3,
-            "operand_bytes_per_step": obytes,
+            "per_depth": per_depth,
+        },
+        "hbm_roof": {
+            "operand_gbs_required": req_bytes / span / 1e9 if span > 0 else None,
+            "operand_gbs_executed": obytes_exec / span / 1e9 if span > 0 else None,
+            "peak_gbs": HBM_PEAK_GBS,
+            "frac_required": req_bytes / span / 1e9 / HBM_PEAK_GBS if span > 0 else None,
+            "frac_executed": obytes_exec / span / 1e9 / HBM_PEAK_GBS if span > 0 else None,
+            "operand_bytes_required_per_step": req_bytes,
+            "operand_bytes_executed_per_step": obytes_exec,
+            "l2_egress_bytes_per_launch": traffic,
+            "l2_egress_gbs": (traffic / (span / launches) / 1e9) if (traffic and span > 0) else None,
+            "l2_egress_frac_hbm": (traffic / (span / launches) / 1e9 / HBM_PEAK_GBS)
+            if (traffic and span > 0) else None,
+            "streaming_read_peak_gbs": stream_peak,
+            "frac_required_of_streaming_peak": (req_bytes / span / 1e9 / stream_peak)
+            if (stream_peak and span > 0) else None,
         },
     }
 
@@ -277,7 +418,7 @@ def main():
         torch.cuda.synchronize()
         pel = time.perf_counter() - t0
         psk = bns.collect(h)
-        same = (psk.adj == sks[0].adj).all() and psk.sepsets == sks[0].sepsets
+        same = (psk.adj == first[0].adj).all() and psk.sepsets == first[0].sepsets
         preq = _sum(psk.stats, "tests_required")
         out["plain_form"] = {"value": preq / pel, "unit": "CI tests/s", "ms_per_step": pel * 1e3,
                              "same_skeleton_and_sepsets": bool(same)}
@@ -285,9 +426,14 @@ def main():
 
     if not a.no_precision:
         out["precision_fp32_vs_fp64"] = precision_report(bns, handles[0], dss[0])
+        if a.precision == 0:
+            out["search_fp32_error"] = search_error_report(bns, handles, alphas, maxd, knobs)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(dss)
     print(json.dumps(out), flush=True)
+    if not parity_ok:
+        print(f"parity failure: {parity_msg}", file=sys.stderr)
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define BNS_VERSION 1
+#define BNS_VERSION 2
 
 typedef enum bns_status {
     BNS_OK = 0,
@@ -109,9 +109,48 @@ typedef struct bns_options {
     uint32_t wave_depths;  /* batched form: per-depth override of test_group for depths
                               d < 32: bit (1u << d) set = one wave per test at depth d */
     uint32_t block_depths; /* same, one workgroup per test; no bit may be set in both */
-    int32_t reserved[2];   /* must be zero */
+    int32_t report_errors; /* batched form, FP32 arithmetic: verification mode (untimed use).
+                              Every executed test is also evaluated in FP64 (from the
+                              table still in LDS, or by counting again) and the relative
+                              FP32 G^2 error |G2_32 - G2_64| / max(G2_64, 1) and the
+                              decisions the FP32 value alone would have flipped are
+                              reported per depth in bns_depth_stats (err_* fields).
+                              Decisions, skeleton and sepsets are those of the normal
+                              search.  0 = off (default) */
+    int32_t workspace_mb;  /* largest device workspace a call may hold, in MiB (datasets
+                              excluded); a call that needs more fails with BNS_E_NOMEM
+                              before any device work.  0 = no limit (default) */
+    int32_t statistic;     /* BNS_STAT_*: the test statistic (default BNS_STAT_G2) */
+    int32_t df_rule;       /* BNS_DF_*: the degrees of freedom (default BNS_DF_DECLARED) */
+    int32_t depth0;        /* batched form, depth 0 (one marginal test per pair):
+                              BNS_DEPTH0_* (default automatic) */
+    int32_t reserved[3];   /* must be zero */
     void *stream;          /* hipStream_t; NULL = default stream */
 } bns_options;
+
+/* Test statistic (Section III-B defines G^2; Section II names Pearson's X^2 as
+ * an alternative test on the same contingency table).  Both are compared with
+ * the chi-square distribution of the same df. */
+enum {
+    BNS_STAT_G2 = 0, /* G^2 = 2 sum N ln(N / E) (the paper's test) */
+    BNS_STAT_X2 = 1  /* X^2 = sum (N - E)^2 / E over cells with E > 0 */
+};
+
+/* Degrees of freedom of a test. */
+enum {
+    BNS_DF_DECLARED = 0, /* (r_X - 1)(r_Y - 1) prod r_Z from the declared cardinalities */
+    BNS_DF_ADJUSTED = 1  /* sum over strata z with N_++z > 0 of (a_z - 1)(b_z - 1), where a_z
+                            and b_z count the non-empty rows N_x+z and columns N_+yz of the
+                            stratum (empty categories and strata dropped); df 0 gives p = 1 */
+};
+
+/* Depth-0 path of the batched form. */
+enum {
+    BNS_DEPTH0_AUTO = 0,    /* the library chooses */
+    BNS_DEPTH0_TESTS = 1,   /* the depth's tests run in the per-depth test kernel */
+    BNS_DEPTH0_PAIRS = 2    /* all pairwise tables at once as one contraction of one-hot
+                               columns (Section IV-B: depth 0 tests every pair) */
+};
 
 /* Fills *opt with the defaults.  opt must not be NULL. */
 void bns_options_default(bns_options *opt);
@@ -192,6 +231,13 @@ typedef struct bns_depth_stats {
     double span_seconds;     /* test-kernel execution span from device clock stamps:
                                 entry of workgroup 0 (dispatched first) to the end of
                                 the last workgroup (always) */
+    /* Verification mode (options.report_errors), else 0: */
+    int64_t err_tests;       /* executed tests whose FP32 statistic was compared with FP64 */
+    int64_t err_flips;       /* of those, tests whose FP32-only decision differs from FP64's
+                                (the re-check band exists to catch these) */
+    double err_max;          /* largest relative FP32 error of the statistic */
+    double err_p50;          /* median */
+    double err_p99;          /* 99th percentile */
 } bns_depth_stats;
 
 /* Learns the skeleton of one dataset.  alpha in (0, 1); max_depth >= -1
@@ -246,7 +292,12 @@ bns_status bns_skeleton_sepset(const bns_skeleton *sk, int32_t i, int32_t j, int
 bns_status bns_skeleton_removals(const bns_skeleton *sk, int32_t *depth, int64_t *sep_off,
                                  int32_t *pool, int64_t pool_cap, int64_t *pool_len);
 
-/* Per-depth counters; up to cap entries written, *n_depths = depths run. */
+/* Per-depth counters; up to cap entries written, *n_depths = depths run.
+ * For a handle of bns_pc_skeleton_batch the counters are that problem's own
+ * (its edges, tests, removals and re-checks; operand_bytes from its sample
+ * count), for its depths up to the last one at which it had a test; the
+ * timing fields (kernel_seconds, span_seconds) are those of the batch's
+ * launch of that depth, shared by all problems of the batch. */
 bns_status bns_skeleton_stats(const bns_skeleton *sk, bns_depth_stats *out, int32_t cap,
                               int32_t *n_depths);
 

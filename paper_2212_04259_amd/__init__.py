@@ -9,10 +9,17 @@ this package only marshals arguments.  See ``_lib`` for the entry points.
 from ._lib import (  # noqa: F401
     BNS_CI_INDEPENDENT,
     BNS_CI_RECHECKED,
+    BNS_DEPTH0_AUTO,
+    BNS_DEPTH0_PAIRS,
+    BNS_DEPTH0_TESTS,
+    BNS_DF_ADJUSTED,
+    BNS_DF_DECLARED,
     BNS_FORM_BATCHED,
     BNS_FORM_PLAIN,
     BNS_PREC_FP32_RECHECK,
     BNS_PREC_FP64,
+    BNS_STAT_G2,
+    BNS_STAT_X2,
     EXPORTS,
     BnsError,
     bns_autotune,

@@ -21,6 +21,9 @@ BNS_OK = 0
 BNS_FORM_BATCHED, BNS_FORM_PLAIN = 0, 1
 BNS_PREC_FP32_RECHECK, BNS_PREC_FP64 = 0, 1
 BNS_CI_INDEPENDENT, BNS_CI_RECHECKED = 1, 2
+BNS_STAT_G2, BNS_STAT_X2 = 0, 1
+BNS_DF_DECLARED, BNS_DF_ADJUSTED = 0, 1
+BNS_DEPTH0_AUTO, BNS_DEPTH0_TESTS, BNS_DEPTH0_PAIRS = 0, 1, 2
 STATUS_NAMES = {0: "BNS_OK", 1: "BNS_E_INVALID_ARG", 2: "BNS_E_VALUE_RANGE",
                 3: "BNS_E_TABLE_TOO_LARGE", 4: "BNS_E_NOMEM", 5: "BNS_E_DEVICE",
                 6: "BNS_E_INTERNAL"}
@@ -49,8 +52,10 @@ class bns_options(ctypes.Structure):
                 ("units_per_group", ctypes.c_int32), ("test_group", ctypes.c_int32),
                 ("max_replicas", ctypes.c_int32), ("tickets_per_grab", ctypes.c_int32),
                 ("ticket_runs", ctypes.c_int32), ("wave_depths", ctypes.c_uint32),
-                ("block_depths", ctypes.c_uint32), ("reserved", ctypes.c_int32 * 2),
-                ("stream", ctypes.c_void_p)]
+                ("block_depths", ctypes.c_uint32), ("report_errors", ctypes.c_int32),
+                ("workspace_mb", ctypes.c_int32), ("statistic", ctypes.c_int32),
+                ("df_rule", ctypes.c_int32), ("depth0", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3), ("stream", ctypes.c_void_p)]
 
 
 class bns_ci_test(ctypes.Structure):
@@ -64,7 +69,9 @@ class bns_depth_stats(ctypes.Structure):
                 ("tests_executed", ctypes.c_int64), ("removed", ctypes.c_int64),
                 ("rechecks", ctypes.c_int64), ("tickets", ctypes.c_int64),
                 ("operand_bytes", ctypes.c_double), ("kernel_seconds", ctypes.c_double),
-                ("span_seconds", ctypes.c_double)]
+                ("span_seconds", ctypes.c_double), ("err_tests", ctypes.c_int64),
+                ("err_flips", ctypes.c_int64), ("err_max", ctypes.c_double),
+                ("err_p50", ctypes.c_double), ("err_p99", ctypes.c_double)]
 
 
 _lib = None

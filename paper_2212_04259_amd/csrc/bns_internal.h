@@ -65,6 +65,17 @@ struct DepthStatDev {
     unsigned long long t_end;        // latest workgroup end
 };
 
+// Per-problem, per-depth counters of a multi-dataset search (problem k,
+// depth d at index k * kMaxDepths + d).
+struct PStatDev {
+    unsigned long long edges;     // edges of the problem alive when the depth started
+    unsigned long long tickets;   // tests of the depth's sequential order (all ranks)
+    unsigned long long required;  // canonical tests: per edge, up to its first accepting one
+    unsigned long long removed;
+    unsigned long long executed;  // tests run (speculative included)
+    unsigned long long rechecks;
+};
+
 // Device-resident control block of a skeleton search.
 struct Ctl {
     int32_t depth;         // depth being built / run

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -90,8 +91,19 @@ static bns_status read_options(const bns_options *in, bns_options *out) {
         return fail(BNS_E_INVALID_ARG, "options.ticket_runs must be 0, 1 or 2");
     if ((out->wave_depths & out->block_depths) != 0u)
         return fail(BNS_E_INVALID_ARG, "options.wave_depths and options.block_depths share a depth");
-    for (int i = 0; i < 2; ++i)
+    if (out->report_errors < 0 || out->report_errors > 1)
+        return fail(BNS_E_INVALID_ARG, "options.report_errors must be 0 or 1");
+    if (out->workspace_mb < 0) return fail(BNS_E_INVALID_ARG, "options.workspace_mb must be >= 0");
+    if (out->statistic != BNS_STAT_G2 && out->statistic != BNS_STAT_X2)
+        return fail(BNS_E_INVALID_ARG, "options.statistic must be a BNS_STAT_* value");
+    if (out->df_rule != BNS_DF_DECLARED && out->df_rule != BNS_DF_ADJUSTED)
+        return fail(BNS_E_INVALID_ARG, "options.df_rule must be a BNS_DF_* value");
+    if (out->depth0 < BNS_DEPTH0_AUTO || out->depth0 > BNS_DEPTH0_PAIRS)
+        return fail(BNS_E_INVALID_ARG, "options.depth0 must be a BNS_DEPTH0_* value");
+    for (int i = 0; i < 3; ++i)
         if (out->reserved[i] != 0) return fail(BNS_E_INVALID_ARG, "options.reserved must be zero");
+    if (out->statistic != BNS_STAT_G2 || out->df_rule != BNS_DF_DECLARED || out->depth0 == BNS_DEPTH0_PAIRS)
+        return fail(BNS_E_INVALID_ARG, "options.statistic, df_rule and depth0 = PAIRS are not available yet");
     return BNS_OK;
 }
 
@@ -144,6 +156,8 @@ struct DevCtx {
     std::mutex mu;
     // skeleton search
     DevBuf setup, adj, adjbits, nbr, ipos, deg, rowcnt, rowbase, edges_tmp, edges, min_accept, rdepth, pool, ctl;
+    DevBuf pstat, ecnt;  // per-problem counters of multi-dataset searches
+    DevBuf err_val, err_tag, err_cnt;  // verification log
     // bytes of the last search set-up uploaded into `setup` (a repeated
     // search skips the upload)
     std::vector<char> setup_last;
@@ -350,6 +364,14 @@ extern "C" bns_status bns_dataset_wrap_device(const uint8_t *d_data, int64_t ld,
 
 extern "C" void bns_dataset_free(bns_dataset *ds) { delete ds; }
 
+// Device workspace a call needs against options.workspace_mb.
+static bns_status check_workspace(const bns_options &o, double need_bytes, const char *what) {
+    if (o.workspace_mb > 0 && need_bytes > (double)o.workspace_mb * 1048576.0)
+        return fail(BNS_E_NOMEM, "%s needs %.1f MiB of device workspace, above options.workspace_mb = %d",
+                    what, need_bytes / 1048576.0, o.workspace_mb);
+    return BNS_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Tiles
 // ---------------------------------------------------------------------------
@@ -426,6 +448,21 @@ extern "C" bns_status bns_ci_batch(const bns_dataset *ds, const bns_ci_test *tes
                 return fail(BNS_E_INVALID_ARG, "test %lld: bad conditioning variable %d", (long long)t, zv);
         }
         st = check_table(ds->cards, q.x, q.y, q.n_z ? z_pool + q.z_offset : nullptr, q.n_z, tile);
+        if (st != BNS_OK) return st;
+    }
+    {
+        double need = (double)(sizeof(CiTestDev) + sizeof(CiOutDev)) * (double)n_tests +
+                      4.0 * (double)std::max<int64_t>(z_pool_len, 1);
+        if (tables_out) {
+            int64_t tab_words = 0;
+            for (int64_t t = 0; t < n_tests; ++t) {
+                int64_t T = (int64_t)ds->cards[tests[t].x] * ds->cards[tests[t].y];
+                for (int k = 0; k < tests[t].n_z; ++k) T *= ds->cards[z_pool[tests[t].z_offset + k]];
+                tab_words = std::max(tab_words, table_offsets[t] + T);
+            }
+            need += 4.0 * (double)tab_words + 8.0 * (double)n_tests;
+        }
+        st = check_workspace(o, need, "bns_ci_batch");
         if (st != BNS_OK) return st;
     }
     DeviceGuard dg(ds->device);
@@ -570,6 +607,8 @@ static bns_status dev_error(int32_t e) {
 }
 
 static const int kDepthsPerLaunch = 8;
+// Verification log entries (executed tests of one search) at most.
+static const int64_t kErrLogEntries = 8 << 20;
 // Split depths: merge tables (words) shared by a depth's tickets, the largest
 // ticket count that is split, and default chunk / occupancy targets.
 static const int64_t kSplitWords = 8 << 20;
@@ -680,6 +719,22 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     const size_t o_v2p = al8(o_binom + sizeof(uint64_t) * B.size());
     const size_t o_cards = al8(o_v2p + sizeof(int32_t) * (size_t)G);
     const size_t setup_bytes = al8(o_cards + (size_t)G);
+    const bool per_prob = P > 1;
+    const bool verify = o.report_errors != 0 && o.precision == BNS_PREC_FP32_RECHECK;
+    const int64_t err_cap = verify ? kErrLogEntries : 0;
+    const size_t rbytes = ((size_t)adj_total + 7) & ~(size_t)7;  // removal depths, padded for 8-byte copies
+    {
+        // every workspace buffer of the search (removal records: the first
+        // launch's share; later growth is checked when it happens)
+        const double bits = 8.0 * (double)std::min<int64_t>(std::max<int64_t>(bit_total, 1), kSmallBitWords);
+        const double need = (double)setup_bytes + 9.0 * (double)adj_total + bits + (double)rbytes +
+                            16.0 * G + (2.0 * sizeof(EdgeRec) + 8.0) * (double)pairs_total + sizeof(Ctl) +
+                            4.0 * (double)kSplitWords + 4.0 * (double)kSplitTickets +
+                            4.0 * 1024 + (per_prob ? sizeof(PStatDev) * (double)P * kMaxDepths + 8.0 * pairs_total : 0.0) +
+                            8.0 * (double)err_cap;
+        st = check_workspace(o, need, "the skeleton search");
+        if (st != BNS_OK) return st;
+    }
     HIP_TRY(dc.setup.ensure(setup_bytes));
     HIP_TRY(dc.pinned(setup_bytes));
     {
@@ -701,7 +756,6 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     HIP_TRY(dc.ipos.ensure(sizeof(int32_t) * (size_t)adj_total));
     // bit rows are used only by small searches (at most kSmallBitWords words)
     HIP_TRY(dc.adjbits.ensure(sizeof(uint64_t) * (size_t)std::min<int64_t>(std::max<int64_t>(bit_total, 1), kSmallBitWords)));
-    const size_t rbytes = ((size_t)adj_total + 7) & ~(size_t)7;  // removal depths, padded for 8-byte copies
     HIP_TRY(dc.rdepth.ensure(rbytes));
     HIP_TRY(dc.deg.ensure(sizeof(int32_t) * (size_t)G));
     HIP_TRY(dc.rowcnt.ensure(sizeof(int32_t) * (size_t)G));
@@ -711,6 +765,13 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     HIP_TRY(dc.min_accept.ensure(sizeof(unsigned long long) * (size_t)pairs_total));
     HIP_TRY(dc.ctl.ensure(sizeof(Ctl)));
     HIP_TRY(dc.pool.ensure(sizeof(int32_t) * 1024));
+    if (verify) {
+        HIP_TRY(dc.err_val.ensure(sizeof(float) * (size_t)err_cap));
+        HIP_TRY(dc.err_tag.ensure(sizeof(uint32_t) * (size_t)err_cap));
+        HIP_TRY(dc.err_cnt.ensure(sizeof(unsigned long long)));
+    }
+    HIP_TRY(dc.pstat.ensure(per_prob ? sizeof(PStatDev) * (size_t)P * kMaxDepths : 256));
+    HIP_TRY(dc.ecnt.ensure(per_prob ? sizeof(uint32_t) * 2 * (size_t)pairs_total : 256));
     if (!dc.split_tab.p || dc.split_dirty) {
         HIP_TRY(dc.split_tab.ensure(sizeof(uint32_t) * (size_t)kSplitWords));
         HIP_TRY(dc.split_cnt.ensure(sizeof(uint32_t) * (size_t)kSplitTickets));
@@ -740,6 +801,15 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     a.edges_tmp = dc.edges_tmp.as<EdgeRec>();
     a.edges = dc.edges.as<EdgeRec>();
     a.min_accept = dc.min_accept.as<unsigned long long>();
+    a.pstat = dc.pstat.as<PStatDev>();
+    a.ecnt = dc.ecnt.as<uint32_t>();
+    a.per_prob = per_prob ? 1 : 0;
+    if (verify) {
+        a.err_val = dc.err_val.as<float>();
+        a.err_tag = dc.err_tag.as<uint32_t>();
+        a.err_cnt = dc.err_cnt.as<unsigned long long>();
+        a.err_cap = err_cap;
+    }
     a.rdepth = dc.rdepth.as<int8_t>();
     a.pool = dc.pool.as<int32_t>();
     a.ctl = dc.ctl.as<Ctl>();
@@ -785,7 +855,7 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     // host reads the control block once per launch.  A depth with no tests
     // marks the search done and the kernels of any later sequence in the same
     // launch return at once.
-    const bool use_graph = o.use_graph != 0 && !o.timing;
+    const bool use_graph = o.use_graph != 0 && !o.timing && !verify;
     GraphEntry *ge = nullptr;
     const int per_launch = (use_graph || o.timing) ? kDepthsPerLaunch : 1;
     std::vector<bns_depth_stats> stats;
@@ -810,6 +880,9 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
             if (d + i > 0) slots += alive * (unsigned long long)(d + i + 3);
         const size_t need = (size_t)(pool_used + slots);
         if (need > dc.pool.bytes / sizeof(int32_t)) {
+            st = check_workspace(o, 4.0 * (double)std::max(need, 2 * dc.pool.bytes / sizeof(int32_t)),
+                                 "the skeleton search's removal records");
+            if (st != BNS_OK) return st;
             DevBuf nb;
             HIP_TRY(nb.ensure(sizeof(int32_t) * std::max(need, 2 * dc.pool.bytes / sizeof(int32_t))));
             if (pool_used)
@@ -910,6 +983,54 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
             HIP_TRY(hipMemcpyAsync((char *)dc.hres + rbytes, dc.pool.p, pbytes, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
     }
+    // Verification log: relative FP32 errors by (problem, depth).
+    std::vector<std::vector<std::vector<float>>> errv;
+    std::vector<std::vector<int64_t>> errflip;
+    if (verify) {
+        unsigned long long cnt = 0;
+        HIP_TRY(hipMemcpyAsync(&cnt, dc.err_cnt.p, sizeof(cnt), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if ((int64_t)cnt > err_cap)
+            return fail(BNS_E_NOMEM, "verification log overflow: %llu tests, room for %lld", cnt, (long long)err_cap);
+        std::vector<float> hv((size_t)cnt);
+        std::vector<uint32_t> ht((size_t)cnt);
+        if (cnt) {
+            HIP_TRY(hipMemcpyAsync(hv.data(), dc.err_val.p, sizeof(float) * (size_t)cnt, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(ht.data(), dc.err_tag.p, sizeof(uint32_t) * (size_t)cnt, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        errv.assign((size_t)P, std::vector<std::vector<float>>(kMaxDepths));
+        errflip.assign((size_t)P, std::vector<int64_t>(kMaxDepths, 0));
+        for (size_t i = 0; i < (size_t)cnt; ++i) {
+            const uint32_t k = ht[i] >> 16, dd = ht[i] & 0xffu;
+            if (k >= (uint32_t)P || dd >= (uint32_t)kMaxDepths) return fail(BNS_E_INTERNAL, "corrupt verification record");
+            errv[k][dd].push_back(hv[i]);
+            errflip[k][dd] += (ht[i] >> 8) & 1u;
+        }
+    }
+    auto fill_err = [&](bns_depth_stats &r, int k, int dd) {
+        if (!verify || dd >= kMaxDepths) return;
+        std::vector<float> &v = errv[(size_t)k][(size_t)dd];
+        r.err_tests = (int64_t)v.size();
+        r.err_flips = errflip[(size_t)k][(size_t)dd];
+        if (v.empty()) return;
+        std::sort(v.begin(), v.end());
+        // nearest-rank percentiles
+        auto rank = [&](double q) {
+            size_t i = (size_t)std::ceil(q * (double)v.size());
+            return (double)v[std::min(v.size() - 1, i ? i - 1 : 0)];
+        };
+        r.err_max = (double)v.back();
+        r.err_p50 = rank(0.5);
+        r.err_p99 = rank(0.99);
+    };
+    // Per-problem counters of a multi-dataset search (small: P x 64 records).
+    std::vector<PStatDev> hps;
+    if (per_prob) {
+        hps.resize((size_t)P * kMaxDepths);
+        HIP_TRY(hipMemcpyAsync(hps.data(), dc.pstat.p, sizeof(PStatDev) * hps.size(), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     const char *hres = (const char *)dc.hres;
     const int8_t *hdep = (const int8_t *)hres;
     const int32_t *hpool = (const int32_t *)(hres + rbytes);
@@ -930,7 +1051,27 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
                 sk->adj[e] = (dd < 0 && i != j) ? 1 : 0;
                 if (dd == 0) sk->sepoff[e] = 0;  // empty set
             }
-        sk->stats = stats;
+        if (!per_prob) {
+            sk->stats = stats;
+            for (size_t dd = 0; dd < sk->stats.size(); ++dd) fill_err(sk->stats[dd], k, (int)dd);
+            continue;
+        }
+        // This problem's own counters, up to its last depth with a test; the
+        // launch timings (kernel_seconds, span_seconds) are the batch's.
+        for (size_t dd = 0; dd < stats.size() && dd < (size_t)kMaxDepths; ++dd) {
+            const PStatDev &ps = hps[(size_t)k * kMaxDepths + dd];
+            if (ps.tickets == 0) break;
+            bns_depth_stats r = stats[dd];
+            r.edges = (int64_t)ps.edges;
+            r.tickets = (int64_t)ps.tickets;
+            r.tests_required = (int64_t)ps.required;
+            r.tests_executed = (int64_t)ps.executed;
+            r.removed = (int64_t)ps.removed;
+            r.rechecks = (int64_t)ps.rechecks;
+            r.operand_bytes = (double)ps.executed * (double)(dd + 2) * (double)ds[k]->m;
+            fill_err(r, k, (int)dd);
+            sk->stats.push_back(r);
+        }
     }
     for (unsigned long long q = 0; q < pool_used;) {
         const int32_t k = hpool[q], i = hpool[q + 1], j = hpool[q + 2];

@@ -42,6 +42,11 @@ struct TestOut {
     int64_t df;
     int32_t flags;   // bit 0 independent, bit 1 rechecked
     int32_t err;     // DevError
+    // verification (run_test<true>): the first-round statistic, its FP64
+    // value, and whether the first round's decision differs from FP64's
+    double g2_first;
+    double g2_ref;
+    int32_t flip;
 };
 
 // ---------------------------------------------------------------------------
@@ -836,10 +841,14 @@ BNS_INLINE Tail group_tail(const Grp &g, int64_t df, double g2, TestSh &t) {
 // gtab (may be null) receives the exact table.  src: the samples counted, or
 // the merged table of a split test to evaluate, or a merge target (then only
 // the chunk [s0, s1) is counted and added there; no G^2, no decision).
+template <bool kVerify = false>
 BNS_INLINE TestOut run_test(const Grp &g, TestSh &t, uint32_t *lds, uint32_t W, const Tile &tile,
                             double alpha, uint32_t *gtab, const Src &src) {
     TestOut o;
     o.flags = 0;
+    o.g2_first = 0.0;
+    o.g2_ref = 0.0;
+    o.flip = 0;
     const uint32_t lo = lds_offset(lds);
     const uint32_t addr_words = lo < 65536u ? (65536u - lo) / 4u : 0u;
     const Plan P = make_plan(t, W, src.gsrc ? 0 : tile.max_rep_log2, g.size, src.s1 - src.s0,
@@ -856,7 +865,7 @@ BNS_INLINE TestOut run_test(const Grp &g, TestSh &t, uint32_t *lds, uint32_t W, 
     // fitted in one pass, otherwise by a second counting pass.
     const uint32_t *tab = nullptr;
     bool fp64 = tile.fp64 != 0;
-    double g2 = 0.0, p = 1.0;
+    double g2 = 0.0, p = 1.0, p_first = 1.0;
     for (int round = 0; round < 2; ++round) {
         g2 = table_pass(g, t, P, lds, round == 0 ? gtab : nullptr, src, fp64, &tab);
         if (src.gdst) {  // merge only: no statistic, no decision
@@ -866,6 +875,10 @@ BNS_INLINE TestOut run_test(const Grp &g, TestSh &t, uint32_t *lds, uint32_t W, 
         }
         Tail tl = group_tail(g, P.df, g2, t);
         p = tl.p;
+        if (round == 0) {
+            o.g2_first = g2;
+            p_first = p;
+        }
         if (fp64 || P.df <= 0) break;
         const double gap = fabs(p - alpha);
         // propagate the FP32 error bound of G^2 through the tail's slope
@@ -883,6 +896,18 @@ BNS_INLINE TestOut run_test(const Grp &g, TestSh &t, uint32_t *lds, uint32_t W, 
     o.g2 = g2;
     o.p = p;
     if (p > alpha) o.flags |= 1;
+    if (kVerify) {
+        // FP64 value of the statistic: the decision's own when it was FP64,
+        // else from the table still in LDS (one pass) or by counting again.
+        double g64 = g2, p64 = p;
+        if (!fp64 && !(o.flags & 2) && P.df > 0) {
+            if (P.nchunks == 1) g64 = g2_fp64_resident(g, t, P, tab);
+            else g64 = table_pass(g, t, P, lds, nullptr, src, true, &tab);
+            p64 = group_tail(g, P.df, g64, t).p;
+        }
+        o.g2_ref = g64;
+        o.flip = ((p_first > alpha) != (p64 > alpha)) ? 1 : 0;
+    }
     return o;
 }
 

@@ -29,6 +29,19 @@ struct DepthArgs {
     EdgeRec *edges_tmp;
     EdgeRec *edges;           // sorted by levels, descending
     unsigned long long *min_accept;
+    // Multi-dataset searches (per_prob = 1): per-problem counters, and per
+    // edge of the current depth the tests executed and re-checked
+    // (ecnt[2 e], ecnt[2 e + 1]), summed by problem at removal time.
+    PStatDev *pstat;
+    uint32_t *ecnt;
+    int32_t per_prob;
+    int32_t pad3;
+    // Verification mode (err_val non-null): every executed test appends its
+    // relative FP32 error and a tag (problem << 16 | flip << 8 | depth).
+    float *err_val;
+    uint32_t *err_tag;
+    unsigned long long *err_cnt;  // entries appended (may exceed err_cap: overflow)
+    int64_t err_cap;
     int8_t *rdepth;           // per pair (problem block), removal depth or -1
     int32_t *pool;            // removal records of depth >= 1: problem, i, j, sepset
     Ctl *ctl;

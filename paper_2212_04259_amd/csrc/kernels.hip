@@ -102,9 +102,16 @@ __global__ void k_init_search(DepthArgs A) {
             A.adjbits[P.bit_off + e] = word;
         }
     }
+    if (A.per_prob && blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < kMaxDepths; i += blockDim.x) {
+            PStatDev z = {};
+            A.pstat[(int64_t)pi * kMaxDepths + i] = z;
+        }
+    }
     if (pi == 0 && blockIdx.x == 0) {
         Ctl *c = A.ctl;
         if (threadIdx.x == 0) {
+            if (A.err_cnt) *A.err_cnt = 0ull;
             c->depth = 0;
             c->done = 0;
             c->error = 0;
@@ -220,6 +227,7 @@ BNS_INLINE void edges_row(const DepthArgs &A, Ctl *c, int g, unsigned int *hist)
     const int64_t base = A.rowbase[g];
     const uint64_t lt = lanes_below_mask();
     int cnt = 0, hi = 0;
+    unsigned long long tk_sum = 0;  // this lane's tests (per-problem counters)
     for (int u0 = 0; u0 < n; u0 += 64) {
         const int u = u0 + lane;
         const bool a = (u < n) && row[u];
@@ -258,9 +266,18 @@ BNS_INLINE void edges_row(const DepthArgs &A, Ctl *c, int g, unsigned int *hist)
             e.levels = ntot ? 64 - __clzll(ntot) : 0;
             atomicAdd(&hist[e.levels], 1u);
             A.edges_tmp[base + hi + __popcll(mhi & lt)] = e;
+            tk_sum += ntot;
         }
         cnt += __popcll(mask);
         hi += __popcll(mhi);
+    }
+    if (A.per_prob && d < kMaxDepths) {
+        tk_sum = wave_sum(tk_sum);
+        if (lane == 0) {
+            PStatDev &ps = A.pstat[(int64_t)pi * kMaxDepths + d];
+            atomicAdd(&ps.edges, (unsigned long long)hi);
+            if (tk_sum) atomicAdd(&ps.tickets, tk_sum);
+        }
     }
 }
 
@@ -378,7 +395,8 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
                 (unsigned long long)max(A.units_per_group, 1) * groups / total;
             const unsigned long long by_len = (unsigned long long)(A.m_max / A.split_min);
             const unsigned long long cc = min(min(want, by_len), 65536ull);
-            cap = (unsigned long long)A.split_words / total;
+            // whole 128-byte lines per ticket: no two tickets' tables share a line
+            cap = ((unsigned long long)A.split_words / total) & ~31ull;
             if (cc >= 2 && cap >= 64) {
                 const long long per = (A.m_max + (long long)cc - 1) / (long long)cc;
                 Lc = (per + 1023) & ~1023ll;
@@ -449,6 +467,10 @@ BNS_INLINE void scatter_edges(const DepthArgs &A, Ctl *c, unsigned long long fir
         if (valid) {
             A.edges[pos] = r;
             A.min_accept[pos] = ~0ull;
+            if (A.per_prob) {
+                A.ecnt[2 * (uint64_t)pos] = 0u;
+                A.ecnt[2 * (uint64_t)pos + 1] = 0u;
+            }
         }
     }
 }
@@ -677,6 +699,7 @@ BNS_INLINE void prepare_block(const DepthArgs &A, Ctl *c, int d, SmallSh &sh) {
     if (sh.done) return;
     // pass 2: edge records in level order, one thread per row word
     for (int i = threadIdx.x; i < NS; i += kSmallThreads) {
+        unsigned long long n_e = 0, n_tk = 0;  // per-problem counters of this slice
         const BitItem it = bit_item(A, sh, i >> lgL);
         const int s0 = (i & ((1 << lgL) - 1)) * sbits;
         const ProbDev &P = small_prob(A, sh, it.pi);
@@ -712,6 +735,17 @@ BNS_INLINE void prepare_block(const DepthArgs &A, Ctl *c, int d, SmallSh &sh) {
             const unsigned int slot = atomicAdd(&sh.cursor[e.levels], 1u);
             A.edges[slot] = e;
             A.min_accept[slot] = ~0ull;
+            if (A.per_prob) {
+                A.ecnt[2 * (uint64_t)slot] = 0u;
+                A.ecnt[2 * (uint64_t)slot + 1] = 0u;
+                ++n_e;
+                n_tk += e.n;
+            }
+        }
+        if (n_e && d < kMaxDepths) {
+            PStatDev &ps = A.pstat[(int64_t)it.pi * kMaxDepths + d];
+            atomicAdd(&ps.edges, n_e);
+            if (n_tk) atomicAdd(&ps.tickets, n_tk);
         }
     }
 }
@@ -755,7 +789,7 @@ struct Desc {
     int64_t e;
     unsigned long long tk;  // ticket
     int32_t chunk;          // sample chunk of the ticket (split depths)
-    int32_t pad;
+    int32_t prob;
     int32_t valid;
     int32_t ncols;
     uint16_t var[kMaxCols];  // variable ids (n <= 65535)
@@ -826,6 +860,7 @@ BNS_INLINE void decode_ticket(const DepthArgs &A, const unsigned long long *lvl_
     q.alpha = P.alpha;
     q.r = r;
     q.e = e;
+    q.prob = rec.prob;
     q.ncols = d + 2;
     q.var[0] = (uint16_t)rec.i;
     q.var[1] = (uint16_t)rec.j;
@@ -960,7 +995,9 @@ struct Batch {
 // LGB: log2 of the run of consecutive units dealt to a grab counter (a
 // template parameter: the kernel's registers are tight, and the instance for
 // single units keeps the shortest arithmetic).
-template <int LGB>
+// VERIFY: the verification instance (every test also evaluated in FP64 and
+// its FP32 error logged); the timed searches use the other.
+template <int LGB, bool VERIFY>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k_depth_tests(DepthArgs A) {
     extern __shared__ uint32_t lds[];
     __shared__ TestSh tsh[kWaves];
@@ -1117,37 +1154,60 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
                 }
             }
             for (;;) {
-                const TestOut o = run_test(g, t, region, W, A.tile, uni(q.alpha), nullptr, src);
+                const TestOut o = run_test<VERIFY>(g, t, region, W, A.tile, uni(q.alpha), nullptr, src);
                 if (g.rank == 0) tal_bytes[ti] += (double)q.ncols * (double)(src.s1 - src.s0);
                 if (src.gdst) {
-                    // Device-scope atomics are performed at the device's
-                    // coherence point; waiting for this group's table atomics
-                    // (workgroup-scope release) before the chunk is counted
-                    // orders them before the counter, and the evaluating
-                    // group reads the table with device-scope loads issued
-                    // after it has seen the final count.  An agent-scope
-                    // fence would also write back and invalidate this XCD's
-                    // L2, evicting every other test's columns.
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    // Every access to a merge table and its chunk counter is
+                    // an agent-scope atomic, so each word has one order of
+                    // updates seen by all XCDs.  Each wave of the group has
+                    // consumed the values its adds returned, so its adds are
+                    // performed before the barrier; the barrier orders them
+                    // before rank 0's counter increment, a release at agent
+                    // scope.  The group that counts the last chunk acquires
+                    // at agent scope with the same increment, and its table
+                    // loads come after it: every chunk's adds are visible.
                     g.sync();
                     uint32_t prev = 0;
-                    if (g.rank == 0) prev = atomicAdd(&A.split_cnt[q.tk], 1u);
+                    if (g.rank == 0)
+                        prev = __hip_atomic_fetch_add(&A.split_cnt[q.tk], 1u, __ATOMIC_ACQ_REL,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
                     prev = g.bcast(prev, t);
                     if (prev + 1 != nch) break;
-                    if (g.rank == 0) A.split_cnt[q.tk] = 0u;
+                    // the counter is not touched again in this launch
+                    if (g.rank == 0)
+                        __hip_atomic_store(&A.split_cnt[q.tk], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     src = Src{gt, nullptr, 0, 0};  // evaluate the merged table
                     continue;
                 }
                 if (src.gsrc) {
+                    // cleared with agent-scope atomic stores (after the last
+                    // read of the table, which the FP64 re-check may repeat);
+                    // the next use of these words is by a later launch
                     g.sync();
                     const uint32_t T = (uint32_t)table_cells(t);
-                    for (uint32_t i = g.rank; i < T; i += g.size) gt[i] = 0u;
+                    for (uint32_t i = g.rank; i < T; i += g.size)
+                        __hip_atomic_store(gt + i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
                 if (g.rank == 0) {
                     ++tal_exec[ti];
                     if (o.flags & 2) ++tal_re[ti];
                     if (o.err) c->error = o.err;
                     if (o.flags & 1) atomicMin(&A.min_accept[q.e], q.r);
+                    if (VERIFY && !src.gdst) {
+                        const unsigned long long k = atomicAdd(A.err_cnt, 1ull);
+                        if ((int64_t)k < A.err_cap) {
+                            const double ref = o.g2_ref;
+                            A.err_val[k] = (float)(fabs(o.g2_first - ref) / fmax(fabs(ref), 1.0));
+                            A.err_tag[k] = ((uint32_t)q.prob << 16) | ((uint32_t)o.flip << 8) | (uint32_t)d;
+                        }
+                    }
+                    if (A.per_prob) {
+                        __hip_atomic_fetch_add(&A.ecnt[2 * (uint64_t)q.e], 1u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                        if (o.flags & 2)
+                            __hip_atomic_fetch_add(&A.ecnt[2 * (uint64_t)q.e + 1], 1u, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                    }
                 }
                 break;
             }
@@ -1280,6 +1340,32 @@ BNS_INLINE void apply_one(const DepthArgs &A, Ctl *c, int d, bool valid, const E
     A.rdepth[ji] = (int8_t)d;
 }
 
+// Per-problem counters of the edges held by the wave's lanes (valid lanes):
+// one atomic per distinct problem and counter.
+BNS_INLINE void tally_by_problem(const DepthArgs &A, int d, bool valid, int prob, unsigned long long req,
+                                 unsigned long long rem, unsigned long long ex, unsigned long long re) {
+    if (d >= kMaxDepths) return;
+    const int lane = threadIdx.x & 63;
+    uint64_t todo = __ballot(valid);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int P = __shfl(prob, leader, 64);
+        const bool mine = valid && prob == P;
+        const unsigned long long s0 = wave_sum(mine ? req : 0ull);
+        const unsigned long long s1 = wave_sum(mine ? rem : 0ull);
+        const unsigned long long s2 = wave_sum(mine ? ex : 0ull);
+        const unsigned long long s3 = wave_sum(mine ? re : 0ull);
+        if (lane == leader) {
+            PStatDev &ps = A.pstat[(int64_t)P * kMaxDepths + d];
+            if (s0) atomicAdd(&ps.required, s0);
+            if (s1) atomicAdd(&ps.removed, s1);
+            if (s2) atomicAdd(&ps.executed, s2);
+            if (s3) atomicAdd(&ps.rechecks, s3);
+        }
+        todo &= ~__ballot(mine);
+    }
+}
+
 BNS_INLINE void apply_edges(const DepthArgs &A, Ctl *c, int d, unsigned long long first,
                             unsigned long long stride, unsigned long long &req,
                             unsigned long long &rem, const Binom &bn, const ProbDev *probs,
@@ -1303,6 +1389,14 @@ BNS_INLINE void apply_edges(const DepthArgs &A, Ctl *c, int d, unsigned long lon
         }
         if (v0) req += (ma0 == ~0ull) ? r0.n : ma0 + 1;
         if (v1) req += (ma1 == ~0ull) ? r1.n : ma1 + 1;
+        if (A.per_prob) {
+            tally_by_problem(A, d, v0, v0 ? r0.prob : 0, v0 ? ((ma0 == ~0ull) ? r0.n : ma0 + 1) : 0ull,
+                             (v0 && ma0 != ~0ull) ? 1ull : 0ull, v0 ? A.ecnt[2 * e0] : 0u,
+                             v0 ? A.ecnt[2 * e0 + 1] : 0u);
+            tally_by_problem(A, d, v1, v1 ? r1.prob : 0, v1 ? ((ma1 == ~0ull) ? r1.n : ma1 + 1) : 0ull,
+                             (v1 && ma1 != ~0ull) ? 1ull : 0ull, v1 ? A.ecnt[2 * e1] : 0u,
+                             v1 ? A.ecnt[2 * e1 + 1] : 0u);
+        }
         apply_one(A, c, d, v0, r0, ma0, rem, bn, probs, lds_bits, pool_lds);
         if (base + stride < E) apply_one(A, c, d, v1, r1, ma1, rem, bn, probs, lds_bits, pool_lds);
     }
@@ -1486,8 +1580,9 @@ hipError_t launch_depth_prepare(const DepthArgs &a, hipStream_t s) {
 
 // Instance for the search: tickets dealt in runs when its columns exceed the
 // last-level cache's share (grab_block_log2 = kGrabRunLog2), else singly.
-static auto depth_tests_kernel(const DepthArgs &a) -> decltype(&k_depth_tests<0>) {
-    return a.grab_block_log2 ? &k_depth_tests<kGrabRunLog2> : &k_depth_tests<0>;
+static auto depth_tests_kernel(const DepthArgs &a) -> decltype(&k_depth_tests<0, false>) {
+    if (a.err_val) return &k_depth_tests<0, true>;  // verification (the dealing of tickets is irrelevant)
+    return a.grab_block_log2 ? &k_depth_tests<kGrabRunLog2, false> : &k_depth_tests<0, false>;
 }
 
 hipError_t launch_depth_tests(const DepthArgs &a, int grid, hipStream_t s, hipEvent_t start,
@@ -1507,10 +1602,13 @@ hipError_t launch_depth_apply(const DepthArgs &a, hipStream_t s) {
 }
 
 hipError_t allow_dynamic_lds(int bytes) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_depth_tests<kGrabRunLog2>,
+    hipError_t e = hipFuncSetAttribute((const void *)k_depth_tests<kGrabRunLog2, false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_depth_tests<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        e = hipFuncSetAttribute((const void *)k_depth_tests<0, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_depth_tests<0, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 bytes);
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void *)k_ci_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1523,7 +1621,7 @@ hipError_t allow_dynamic_lds(int bytes) {
 
 int depth_tests_max_wg_per_cu(int lds_bytes) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_depth_tests<0>, kWG, (size_t)lds_bytes) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_depth_tests<0, false>, kWG, (size_t)lds_bytes) !=
         hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
@@ -1537,7 +1635,7 @@ int depth_tests_fit_lds(int lds_per_cu) {
     const int target = depth_tests_max_wg_per_cu(4096);
     hipFuncAttributes fa;
     int stat = 16384;
-    if (hipFuncGetAttributes(&fa, (const void *)k_depth_tests<0>) == hipSuccess) stat = (int)fa.sharedSizeBytes;
+    if (hipFuncGetAttributes(&fa, (const void *)k_depth_tests<0, false>) == hipSuccess) stat = (int)fa.sharedSizeBytes;
     if (lds_per_cu <= 0) lds_per_cu = 65536;
     const int share = (lds_per_cu / max(target, 1)) & ~2047;
     int b = (share - stat) & ~255;

@@ -33,6 +33,8 @@ MUTANTS = {
     "no_snapshot": ("if (snap[i * n + k] != j) candA[pA++] = snap[i * n + k];",
                     "if (snap[i * n + k] != j && r->adj[i * n + snap[i * n + k]]) candA[pA++] = snap[i * n + k];"),
     "z_radix_wrong": ("mult *= cards[z[k]];", "mult *= rx;"),
+    "knife_edges_never_counted": ("if (gap < 1e-9) r->knife += 1;", "if (gap < 0.0) r->knife += 1;"),
+    "gap_measured_on_complement": ("double gap = fabs(pv - alpha);", "double gap = fabs((1.0 - pv) - alpha);"),
 }
 
 

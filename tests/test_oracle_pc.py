@@ -224,3 +224,66 @@ def test_order_independence_under_relabelling(orc, seed):
         assert len(S_old) == res.depth[min(i, j), max(i, j)]
         p = orc.ci_test(ds.data, ds.cards, i, j, S_old)[2]
         assert p > 0.05
+
+
+# ---------------------------------------------------------------------------
+# Reading R16: the driver reports the closest p-value to alpha over every test
+# it ran (min |p - alpha|) and the number of knife-edge tests (|p - alpha| <
+# 1e-9).  A p-value source with planted gaps fixes both figures: which tests
+# run is fixed by Algorithm 1 (one marginal test per pair at depth 0, then the
+# frozen-set subsets), and only the planted tests come near alpha.
+# ---------------------------------------------------------------------------
+def _planted_source(plan, default=0.0):
+    calls = []
+
+    def p(x, y, s):
+        calls.append((x, y, s))
+        return plan.get((x, y, s), default)
+    return p, calls
+
+
+def test_knife_edge_report_planted_gaps(orc):
+    a = 0.05
+    plan = {
+        (0, 1, ()): a + 4e-10,   # independent, knife edge
+        (0, 2, ()): a - 2e-10,   # dependent, knife edge, the closest
+        (0, 3, ()): a + 2e-9,    # independent, not a knife edge (gap 2e-9)
+        (2, 3, ()): a - 3e-9,    # dependent, not a knife edge
+    }
+    src, calls = _planted_source(plan)
+    res = orc.pc_skeleton_cb(4, src, alpha=a)
+    # every planted test ran, at depth 0
+    for key in plan:
+        assert key in calls
+    assert res.knife_edges == 2
+    assert res.min_gap == abs((a - 2e-10) - a)
+    # the decisions the planted values imply (strict p > alpha)
+    assert not res.adj[0, 1] and not res.adj[0, 3]
+    assert res.adj[0, 2] and res.adj[2, 3]
+
+
+def test_knife_edge_report_counts_ties_and_later_depths(orc):
+    a = 0.05
+    # depth 0 removes nothing; at depth 1 the tie p == alpha is a knife edge
+    # with gap 0 (and dependent, R4).  S = {0} is also the first subset of
+    # side B of edge 1-2 (a(2) minus 1 = {0, 3}), and side-B repeats are run
+    # (R11): the tie is met twice.  One more planted gap sits at 5e-10.
+    plan = {(1, 2, (0,)): a, (0, 3, (1,)): a + 5e-10}
+    src, calls = _planted_source(plan)
+    res = orc.pc_skeleton_cb(4, src, alpha=a, max_depth=1)
+    assert calls.count((1, 2, (0,))) == 2 and (0, 3, (1,)) in calls
+    assert res.knife_edges == 3
+    assert res.min_gap == 0.0
+    assert res.adj[1, 2]            # the tie does not remove the edge
+    assert not res.adj[0, 3]        # p slightly above alpha does
+    assert res.depth[0, 3] == 1 and res.sepsets[(0, 3)] == (1,)
+
+
+def test_knife_edge_report_far_from_alpha(orc):
+    # no test near alpha: no knife edge, and the gap is the smallest planted one
+    a = 0.01
+    plan = {(0, 1, ()): 0.5, (1, 2, ()): a + 0.0025}
+    src, _ = _planted_source(plan, default=1e-6)
+    res = orc.pc_skeleton_cb(3, src, alpha=a)
+    assert res.knife_edges == 0
+    assert res.min_gap == abs((a + 0.0025) - a)
