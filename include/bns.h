@@ -209,6 +209,28 @@ bns_status bns_ci_batch(const bns_dataset *ds, const bns_ci_test *tests, int64_t
                         const bns_options *opt, double *g2, int64_t *df, double *p,
                         int32_t *flags, int32_t *tables_out, const int64_t *table_offsets);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): bns_ci_batch without any
+ * allocation by the library.  The tests, the conditioning pool and the results
+ * are staged in a fixed device scratch area of BNS_NOALLOC_SCRATCH_BYTES that
+ * the library holds on each device it runs on until the process ends, instead
+ * of library-allocated buffers; no hipMalloc, hipFree or pinned host
+ * allocation happens in the call.  Same arguments, checks, kernels and results
+ * as bns_ci_batch (all pointers are host pointers; outputs may be NULL), minus
+ * the table output.  A call needs 16 n_tests + 4 z_pool_len + 28 n_tests bytes
+ * of scratch (each section rounded up to 256 bytes); a larger one fails with
+ * BNS_E_NOMEM before any device work.  Calls are synchronous (the stream of
+ * opt->stream, NULL = the null stream, is synchronised before returning) and
+ * the library serialises calls per device, so they never overlap on a device
+ * within a process; overlapping calls would race on the shared scratch area,
+ * which keeps the last call's contents.  The dataset must have been created
+ * beforehand (that allocates). */
+#define BNS_NOALLOC_SCRATCH_BYTES (16 << 20)
+bns_status bns_ci_batch_noalloc(const bns_dataset *ds, const bns_ci_test *tests, int64_t n_tests,
+                                const int32_t *z_pool, int64_t z_pool_len, double alpha,
+                                const bns_options *opt, double *g2, int64_t *df, double *p,
+                                int32_t *flags);
+
 /* ---------------------------------------------------------------------- */
 /* PC-stable skeleton (Algorithm 1)                                       */
 /* ---------------------------------------------------------------------- */

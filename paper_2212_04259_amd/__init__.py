@@ -21,11 +21,13 @@ from ._lib import (  # noqa: F401
     BNS_STAT_G2,
     BNS_STAT_X2,
     EXPORTS,
+    NOALLOC_SCRATCH_BYTES,
     BnsError,
     bns_autotune,
     Dataset,
     Skeleton,
     bns_ci_batch,
+    bns_ci_batch_noalloc,
     bns_dataset_create,
     bns_dataset_wrap_device,
     bns_options,

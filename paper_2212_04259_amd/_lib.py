@@ -34,8 +34,9 @@ EXPORTS = [
     "bns_dataset_free", "bns_ci_batch", "bns_pc_skeleton", "bns_pc_skeleton_dataset",
     "bns_pc_skeleton_batch", "bns_skeleton_n_vars", "bns_skeleton_adjacency",
     "bns_skeleton_sepset", "bns_skeleton_removals", "bns_skeleton_stats", "bns_skeleton_free",
-    "bns_autotune",
+    "bns_autotune", "bns_ci_batch_noalloc",
 ]
+NOALLOC_SCRATCH_BYTES = 16 << 20
 
 
 class BnsError(RuntimeError):
@@ -106,6 +107,8 @@ def load():
     L.bns_dataset_free.argtypes = [vp]
     L.bns_ci_batch.restype = i32
     L.bns_ci_batch.argtypes = [vp, vp, i64, vp, i64, dbl, P(bns_options), vp, vp, vp, vp, vp, vp]
+    L.bns_ci_batch_noalloc.restype = i32
+    L.bns_ci_batch_noalloc.argtypes = [vp, vp, i64, vp, i64, dbl, P(bns_options), vp, vp, vp, vp]
     L.bns_pc_skeleton.restype = i32
     L.bns_pc_skeleton.argtypes = [vp, i64, i32, vp, dbl, i32, P(bns_options), P(vp)]
     L.bns_pc_skeleton_dataset.restype = i32
@@ -215,6 +218,27 @@ def bns_ci_batch(ds: Dataset, tests, alpha: float = 0.05, options: bns_options |
     if want_tables:
         out["tables"] = [tabs[offs[t]:offs[t] + sizes[t]] for t in range(n)]
     return out
+
+
+def bns_ci_batch_noalloc(ds: Dataset, tests, alpha: float = 0.05, options: bns_options | None = None):
+    """bns_ci_batch through the allocation-free entry point (no table output).
+    Returns a dict of numpy arrays g2, df, p, flags."""
+    n = len(tests)
+    arr = (bns_ci_test * max(n, 1))()
+    zs = []
+    for t, (x, y, z) in enumerate(tests):
+        arr[t].x, arr[t].y, arr[t].n_z, arr[t].z_offset = int(x), int(y), len(z), len(zs)
+        zs.extend(int(v) for v in z)
+    zpool = np.asarray(zs if zs else [0], dtype=np.int32)
+    g2 = np.zeros(max(n, 1), dtype=np.float64)
+    df = np.zeros(max(n, 1), dtype=np.int64)
+    p = np.zeros(max(n, 1), dtype=np.float64)
+    flags = np.zeros(max(n, 1), dtype=np.int32)
+    o = options if options is not None else bns_options_default()
+    _check(load().bns_ci_batch_noalloc(ds.handle, ctypes.cast(arr, ctypes.c_void_p), n, _ptr(zpool),
+                                       len(zs), float(alpha), ctypes.byref(o), _ptr(g2), _ptr(df),
+                                       _ptr(p), _ptr(flags)))
+    return dict(g2=g2[:n], df=df[:n], p=p[:n], flags=flags[:n])
 
 
 @dataclass

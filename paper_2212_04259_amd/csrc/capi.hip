@@ -377,12 +377,14 @@ static bns_status check_workspace(const bns_options &o, double need_bytes, const
 // ---------------------------------------------------------------------------
 static const int kDefaultLdsBytes = 40 << 10;
 
-static bns_status make_tile(const DevCtx &dc, const bns_options &o, Tile *t, bool search = false) {
-    int lds = o.lds_bytes ? o.lds_bytes : (search && dc.search_lds ? dc.search_lds : kDefaultLdsBytes);
+// Tile of a launch from the options and the device's LDS per workgroup;
+// default_lds: the dynamic LDS used when the options leave it open.
+static bns_status make_tile_for(int max_lds_block, int default_lds, const bns_options &o, Tile *t) {
+    int lds = o.lds_bytes ? o.lds_bytes : default_lds;
     const int static_reserve = 4096;  // TestSh + TicketSh + reductions
-    if (lds + static_reserve > dc.max_lds_block) lds = dc.max_lds_block - static_reserve;
+    if (lds + static_reserve > max_lds_block) lds = max_lds_block - static_reserve;
     lds &= ~255;
-    if (lds < 4096) return fail(BNS_E_DEVICE, "device LDS per workgroup too small (%d bytes)", dc.max_lds_block);
+    if (lds < 4096) return fail(BNS_E_DEVICE, "device LDS per workgroup too small (%d bytes)", max_lds_block);
     if (lds > (64 << 10) - static_reserve) {
         hipError_t e = allow_dynamic_lds(lds);
         if (e != hipSuccess) return fail(BNS_E_DEVICE, "cannot enable %d bytes of dynamic LDS: %s", lds, hipGetErrorString(e));
@@ -396,6 +398,10 @@ static bns_status make_tile(const DevCtx &dc, const bns_options &o, Tile *t, boo
     return BNS_OK;
 }
 
+static bns_status make_tile(const DevCtx &dc, const bns_options &o, Tile *t, bool search = false) {
+    return make_tile_for(dc.max_lds_block, search && dc.search_lds ? dc.search_lds : kDefaultLdsBytes, o, t);
+}
+
 static bns_status check_table(const std::vector<uint8_t> &cards, int x, int y, const int32_t *z,
                               int nz, const Tile &tile) {
     uint64_t rxy = (uint64_t)cards[x] * cards[y];
@@ -407,6 +413,28 @@ static bns_status check_table(const std::vector<uint8_t> &cards, int x, int y, c
     // one stratum (table + marginals) plus the spill words must fit a wave's slice
     if (rxy + cards[x] + cards[y] + 1 + 64 > (uint64_t)(tile.lds_words / kWaves))
         return fail(BNS_E_TABLE_TOO_LARGE, "r_x * r_y of test %d-%d exceeds the LDS budget", x, y);
+    return BNS_OK;
+}
+
+// Host-side checks of a batch of CI tests (ids, disjointness, table sizes).
+static bns_status check_ci_tests(const bns_dataset *ds, const bns_ci_test *tests, int64_t n_tests,
+                                 const int32_t *z_pool, int64_t z_pool_len, const Tile &tile) {
+    const int n = ds->n;
+    for (int64_t t = 0; t < n_tests; ++t) {
+        const bns_ci_test &q = tests[t];
+        if (q.x < 0 || q.x >= n || q.y < 0 || q.y >= n || q.x == q.y)
+            return fail(BNS_E_INVALID_ARG, "test %lld: bad x/y", (long long)t);
+        if (q.n_z < 0 || q.n_z > kMaxZ) return fail(BNS_E_INVALID_ARG, "test %lld: n_z out of [0, %d]", (long long)t, kMaxZ);
+        if (q.n_z > 0 && (q.z_offset < 0 || (int64_t)q.z_offset + q.n_z > z_pool_len))
+            return fail(BNS_E_INVALID_ARG, "test %lld: z range outside z_pool", (long long)t);
+        for (int k = 0; k < q.n_z; ++k) {
+            const int32_t zv = z_pool[q.z_offset + k];
+            if (zv < 0 || zv >= n || zv == q.x || zv == q.y)
+                return fail(BNS_E_INVALID_ARG, "test %lld: bad conditioning variable %d", (long long)t, zv);
+        }
+        bns_status st = check_table(ds->cards, q.x, q.y, q.n_z ? z_pool + q.z_offset : nullptr, q.n_z, tile);
+        if (st != BNS_OK) return st;
+    }
     return BNS_OK;
 }
 
@@ -434,22 +462,8 @@ extern "C" bns_status bns_ci_batch(const bns_dataset *ds, const bns_ci_test *tes
     Tile tile;
     st = make_tile(*dc, o, &tile);
     if (st != BNS_OK) return st;
-    const int n = ds->n;
-    for (int64_t t = 0; t < n_tests; ++t) {
-        const bns_ci_test &q = tests[t];
-        if (q.x < 0 || q.x >= n || q.y < 0 || q.y >= n || q.x == q.y)
-            return fail(BNS_E_INVALID_ARG, "test %lld: bad x/y", (long long)t);
-        if (q.n_z < 0 || q.n_z > kMaxZ) return fail(BNS_E_INVALID_ARG, "test %lld: n_z out of [0, %d]", (long long)t, kMaxZ);
-        if (q.n_z > 0 && (q.z_offset < 0 || (int64_t)q.z_offset + q.n_z > z_pool_len))
-            return fail(BNS_E_INVALID_ARG, "test %lld: z range outside z_pool", (long long)t);
-        for (int k = 0; k < q.n_z; ++k) {
-            const int32_t zv = z_pool[q.z_offset + k];
-            if (zv < 0 || zv >= n || zv == q.x || zv == q.y)
-                return fail(BNS_E_INVALID_ARG, "test %lld: bad conditioning variable %d", (long long)t, zv);
-        }
-        st = check_table(ds->cards, q.x, q.y, q.n_z ? z_pool + q.z_offset : nullptr, q.n_z, tile);
-        if (st != BNS_OK) return st;
-    }
+    st = check_ci_tests(ds, tests, n_tests, z_pool, z_pool_len, tile);
+    if (st != BNS_OK) return st;
     {
         double need = (double)(sizeof(CiTestDev) + sizeof(CiOutDev)) * (double)n_tests +
                       4.0 * (double)std::max<int64_t>(z_pool_len, 1);
@@ -517,6 +531,91 @@ extern "C" bns_status bns_ci_batch(const bns_dataset *ds, const bns_ci_test *tes
         if (p) p[t] = ho[t].p;
         if (flags) flags[t] = ho[t].flags & 3;
     }
+    return BNS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// bns_ci_batch_noalloc: the same tests with no allocation.  The tests, the
+// conditioning pool and the results are staged in `scratch`, a fixed device
+// array of the library (one copy per device, held until the process ends).
+// In host code `scratch` names a host-side stand-in, not device memory: its
+// device address comes from hipGetSymbolAddress, once per device with that
+// device current, and only that address is used.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[BNS_NOALLOC_SCRATCH_BYTES];
+
+static const int kNoallocDevices = 64;
+static std::mutex g_noalloc_mu[kNoallocDevices];   // serialises calls per device
+static void *g_scratch_dev[kNoallocDevices];       // device address of scratch, per device
+static int g_noalloc_cu[kNoallocDevices], g_noalloc_lds[kNoallocDevices];
+
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+extern "C" bns_status bns_ci_batch_noalloc(const bns_dataset *ds, const bns_ci_test *tests, int64_t n_tests,
+                                           const int32_t *z_pool, int64_t z_pool_len, double alpha,
+                                           const bns_options *opt, double *g2, int64_t *df, double *p,
+                                           int32_t *flags) {
+    static_assert(sizeof(bns_ci_test) == sizeof(CiTestDev), "test records are copied as they are");
+    if (!ds) return fail(BNS_E_INVALID_ARG, "dataset is NULL");
+    if (n_tests < 0) return fail(BNS_E_INVALID_ARG, "n_tests < 0");
+    if (n_tests > 0 && !tests) return fail(BNS_E_INVALID_ARG, "tests is NULL");
+    if (z_pool_len < 0 || (z_pool_len > 0 && !z_pool)) return fail(BNS_E_INVALID_ARG, "bad z_pool");
+    if (!(alpha > 0.0 && alpha < 1.0)) return fail(BNS_E_INVALID_ARG, "alpha must be in (0, 1)");
+    if (ds->device < 0 || ds->device >= kNoallocDevices) return fail(BNS_E_DEVICE, "device %d out of range", ds->device);
+    bns_options o;
+    bns_status st = read_options(opt, &o);
+    if (st != BNS_OK) return st;
+    if (n_tests == 0) return BNS_OK;
+    // scratch layout: tests | conditioning pool | g2 | p | df | flags
+    const size_t o_z = al256(sizeof(CiTestDev) * (size_t)n_tests);
+    const size_t o_g2 = o_z + al256(sizeof(int32_t) * (size_t)z_pool_len);
+    const size_t o_p = o_g2 + al256(sizeof(double) * (size_t)n_tests);
+    const size_t o_df = o_p + al256(sizeof(double) * (size_t)n_tests);
+    const size_t o_fl = o_df + al256(sizeof(int64_t) * (size_t)n_tests);
+    const size_t need = o_fl + al256(sizeof(int32_t) * (size_t)n_tests);
+    if (need > (size_t)BNS_NOALLOC_SCRATCH_BYTES)
+        return fail(BNS_E_NOMEM, "bns_ci_batch_noalloc: %lld tests with %lld pool entries need %zu bytes of "
+                    "scratch, above the fixed %d", (long long)n_tests, (long long)z_pool_len, need,
+                    BNS_NOALLOC_SCRATCH_BYTES);
+    const int dev = ds->device;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu[dev]);
+    DeviceGuard dg(dev);
+    if (!dg.ok) return fail(BNS_E_DEVICE, "cannot select device %d", dev);
+    if (!g_scratch_dev[dev]) {
+        // first call on this device (now current): the device copy's address
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        HIP_TRY(hipDeviceGetAttribute(&g_noalloc_cu[dev], hipDeviceAttributeMultiprocessorCount, dev));
+        HIP_TRY(hipDeviceGetAttribute(&g_noalloc_lds[dev], hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        g_scratch_dev[dev] = ptr;
+    }
+    Tile tile;
+    st = make_tile_for(g_noalloc_lds[dev], kDefaultLdsBytes, o, &tile);
+    if (st != BNS_OK) return st;
+    st = check_ci_tests(ds, tests, n_tests, z_pool, z_pool_len, tile);
+    if (st != BNS_OK) return st;
+    char *base = (char *)g_scratch_dev[dev];
+    hipStream_t s = (hipStream_t)o.stream;
+    HIP_TRY(hipMemcpyAsync(base, tests, sizeof(CiTestDev) * (size_t)n_tests, hipMemcpyHostToDevice, s));
+    if (z_pool_len > 0)
+        HIP_TRY(hipMemcpyAsync(base + o_z, z_pool, sizeof(int32_t) * (size_t)z_pool_len, hipMemcpyHostToDevice, s));
+    CiOutSoa soa{(double *)(base + o_g2), (double *)(base + o_p), (int64_t *)(base + o_df),
+                 (int32_t *)(base + o_fl)};
+    const int wg = std::max(1, depth_tests_max_wg_per_cu(tile.lds_words * 4));
+    const int grid = (int)std::min<int64_t>((n_tests + kWaves - 1) / kWaves, (int64_t)g_noalloc_cu[dev] * wg);
+    HIP_TRY(launch_ci_batch(ds->d_data, ds->ld, ds->m, ds->d_cards, (const CiTestDev *)base,
+                            (const int32_t *)(base + o_z), n_tests, alpha, tile, nullptr, nullptr, nullptr,
+                            grid, s, soa));
+    if (g2) HIP_TRY(hipMemcpyAsync(g2, soa.g2, sizeof(double) * (size_t)n_tests, hipMemcpyDeviceToHost, s));
+    if (p) HIP_TRY(hipMemcpyAsync(p, soa.p, sizeof(double) * (size_t)n_tests, hipMemcpyDeviceToHost, s));
+    if (df) HIP_TRY(hipMemcpyAsync(df, soa.df, sizeof(int64_t) * (size_t)n_tests, hipMemcpyDeviceToHost, s));
+    if (flags) HIP_TRY(hipMemcpyAsync(flags, soa.flags, sizeof(int32_t) * (size_t)n_tests, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (flags)
+        for (int64_t t = 0; t < n_tests; ++t) {
+            if (flags[t] >> 8) return fail(BNS_E_TABLE_TOO_LARGE, "test %lld exceeded device limits", (long long)t);
+            flags[t] &= 3;
+        }
     return BNS_OK;
 }
 

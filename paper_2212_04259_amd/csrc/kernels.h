@@ -95,11 +95,19 @@ int depth_tests_max_wg_per_cu(int lds_bytes);
 int depth_tests_fit_lds(int lds_per_cu);  // default dynamic LDS at full occupancy
 hipError_t allow_dynamic_lds(int bytes);  // raises the per-kernel dynamic LDS limit
 
-// Batched CI tests without PC control.
+// Batched CI tests without PC control: results as records (out) or, with
+// out null, as separate arrays (soa).
+struct CiOutSoa {
+    double *g2;
+    double *p;
+    int64_t *df;
+    int32_t *flags;
+};
 hipError_t launch_ci_batch(const uint8_t *data, int64_t ld, int64_t m, const uint8_t *cards,
                            const CiTestDev *tests, const int32_t *zpool, int64_t n_tests,
                            double alpha, Tile tile, CiOutDev *out, uint32_t *tables,
-                           const int64_t *table_off, int grid, hipStream_t s);
+                           const int64_t *table_off, int grid, hipStream_t s,
+                           CiOutSoa soa = CiOutSoa{nullptr, nullptr, nullptr, nullptr});
 
 // Plain per-test form: sample-parallel count of one test into per-block
 // partial tables, then a single-workgroup finish (fixed-order sum, FP64 G^2).

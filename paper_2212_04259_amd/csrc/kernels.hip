@@ -65,7 +65,7 @@ __device__ inline void unrank_serial(const Binom &B, int64_t p, int d, uint64_t 
 
 __global__ void k_ci_batch(const uint8_t *data, int64_t ld, int64_t m, const uint8_t *cards,
                            const CiTestDev *tests, const int32_t *zpool, int64_t n_tests,
-                           double alpha, Tile tile, CiOutDev *out, uint32_t *tables,
+                           double alpha, Tile tile, CiOutDev *out, CiOutSoa soa, uint32_t *tables,
                            const int64_t *table_off);
 __global__ void k_plain_count(const uint8_t *data, int64_t ld, int64_t m, const uint8_t *cards,
                               const PlainTest pt, int64_t spb, uint32_t *partials, int64_t T,
@@ -1647,11 +1647,14 @@ int depth_tests_fit_lds(int lds_per_cu) {
 // Batched CI tests (bns_ci_batch): one test per wave, same device path as the
 // skeleton search.
 // ---------------------------------------------------------------------------
+// Results go to out (one record per test) or, with out null, to the
+// separate arrays of soa (any may be null).
 __global__ __launch_bounds__(kWG) void k_ci_batch(const uint8_t *data, int64_t ld, int64_t m,
                                                   const uint8_t *cards, const CiTestDev *tests,
                                                   const int32_t *zpool, int64_t n_tests,
                                                   double alpha, Tile tile, CiOutDev *out,
-                                                  uint32_t *tables, const int64_t *table_off) {
+                                                  CiOutSoa soa, uint32_t *tables,
+                                                  const int64_t *table_off) {
     extern __shared__ uint32_t lds[];
     __shared__ TestSh tsh[kWaves];
     const int w = threadIdx.x >> 6;
@@ -1689,7 +1692,14 @@ __global__ __launch_bounds__(kWG) void k_ci_batch(const uint8_t *data, int64_t l
             r.df = o.df;
             r.flags = o.flags | (o.err ? (o.err << 8) : 0);
             r.pad = 0;
-            out[ti] = r;
+            if (out) {
+                out[ti] = r;
+            } else {
+                if (soa.g2) soa.g2[ti] = r.g2;
+                if (soa.p) soa.p[ti] = r.p;
+                if (soa.df) soa.df[ti] = r.df;
+                if (soa.flags) soa.flags[ti] = r.flags;
+            }
         }
         gw.sync();
     }
@@ -1698,9 +1708,9 @@ __global__ __launch_bounds__(kWG) void k_ci_batch(const uint8_t *data, int64_t l
 hipError_t launch_ci_batch(const uint8_t *data, int64_t ld, int64_t m, const uint8_t *cards,
                            const CiTestDev *tests, const int32_t *zpool, int64_t n_tests,
                            double alpha, Tile tile, CiOutDev *out, uint32_t *tables,
-                           const int64_t *table_off, int grid, hipStream_t s) {
+                           const int64_t *table_off, int grid, hipStream_t s, CiOutSoa soa) {
     hipLaunchKernelGGL(k_ci_batch, dim3(grid), dim3(kWG), (size_t)tile.lds_words * 4u, s, data, ld,
-                       m, cards, tests, zpool, n_tests, alpha, tile, out, tables, table_off);
+                       m, cards, tests, zpool, n_tests, alpha, tile, out, soa, tables, table_off);
     return hipGetLastError();
 }
 
