@@ -51,6 +51,13 @@ def lib():
         L.orc_ci_test.restype = ctypes.c_int
         L.orc_ci_test.argtypes = [u8p, ctypes.c_int64, ctypes.c_int32, u8p, ctypes.c_int32,
                                   ctypes.c_int32, i32p, ctypes.c_int32, i64p, dp, i64p, dp]
+        L.orc_ci_test_ex.restype = ctypes.c_int
+        L.orc_ci_test_ex.argtypes = [u8p, ctypes.c_int64, ctypes.c_int32, u8p, ctypes.c_int32,
+                                     ctypes.c_int32, i32p, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, i64p, dp, i64p, dp]
+        L.orc_pc_skeleton_ex.restype = ctypes.c_void_p
+        L.orc_pc_skeleton_ex.argtypes = [u8p, ctypes.c_int64, ctypes.c_int32, u8p, ctypes.c_double,
+                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.orc_pc_skeleton.restype = ctypes.c_void_p
         L.orc_pc_skeleton.argtypes = [u8p, ctypes.c_int64, ctypes.c_int32, u8p, ctypes.c_double,
                                       ctypes.c_int32]
@@ -100,8 +107,15 @@ def _check_data(data, cards):
     return data, cards
 
 
-def ci_test(data, cards, x: int, y: int, z=(), return_counts: bool = False):
-    """G^2 test of I(x, y | z).  Returns (g2, df, p) or (g2, df, p, counts)."""
+STAT_G2, STAT_X2 = 0, 1
+DF_DECLARED, DF_ADJUSTED = 0, 1
+
+
+def ci_test(data, cards, x: int, y: int, z=(), return_counts: bool = False, statistic: int = 0,
+            df_rule: int = 0):
+    """Test of I(x, y | z) with G^2 (statistic 0) or Pearson's X^2 (1), df
+    from the declared cards (df_rule 0) or adjusted for empty rows, columns and
+    strata (1).  Returns (stat, df, p) or (stat, df, p, counts)."""
     data, cards = _check_data(data, cards)
     n, m = data.shape
     z = np.ascontiguousarray(list(z), dtype=np.int32)
@@ -114,10 +128,10 @@ def ci_test(data, cards, x: int, y: int, z=(), return_counts: bool = False):
     g2 = ctypes.c_double()
     df = ctypes.c_int64()
     p = ctypes.c_double()
-    rc = lib().orc_ci_test(_ptr(data, ctypes.c_uint8), m, n, _ptr(cards, ctypes.c_uint8), x, y,
-                           _ptr(z, ctypes.c_int32) if len(z) else None, len(z),
-                           _ptr(counts, ctypes.c_int64) if return_counts else None,
-                           ctypes.byref(g2), ctypes.byref(df), ctypes.byref(p))
+    rc = lib().orc_ci_test_ex(_ptr(data, ctypes.c_uint8), m, n, _ptr(cards, ctypes.c_uint8), x, y,
+                              _ptr(z, ctypes.c_int32) if len(z) else None, len(z), int(statistic),
+                              int(df_rule), _ptr(counts, ctypes.c_int64) if return_counts else None,
+                              ctypes.byref(g2), ctypes.byref(df), ctypes.byref(p))
     if rc != 0:
         raise ValueError(f"orc_ci_test failed with {rc}")
     if return_counts:
@@ -176,12 +190,14 @@ def _collect(res_ptr) -> SkeletonResult:
         L.orc_result_free(res_ptr)
 
 
-def pc_skeleton(data, cards, alpha: float = 0.05, max_depth: int = -1) -> SkeletonResult:
-    """PC-stable step 1 with the G^2 test (Algorithm 1 with Section IV-C grouping)."""
+def pc_skeleton(data, cards, alpha: float = 0.05, max_depth: int = -1, statistic: int = 0,
+                df_rule: int = 0) -> SkeletonResult:
+    """PC-stable step 1 with the G^2 test (Algorithm 1 with Section IV-C
+    grouping); statistic and df_rule as in ci_test."""
     data, cards = _check_data(data, cards)
     n, m = data.shape
-    r = lib().orc_pc_skeleton(_ptr(data, ctypes.c_uint8), m, n, _ptr(cards, ctypes.c_uint8),
-                              float(alpha), int(max_depth))
+    r = lib().orc_pc_skeleton_ex(_ptr(data, ctypes.c_uint8), m, n, _ptr(cards, ctypes.c_uint8),
+                                 float(alpha), int(max_depth), int(statistic), int(df_rule))
     if not r:
         raise MemoryError("oracle allocation failed")
     return _collect(r)

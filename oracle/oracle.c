@@ -79,6 +79,15 @@ double orc_gamma_q(double a, double x) {
 int orc_ci_test(const uint8_t *data, int64_t m, int32_t n_vars, const uint8_t *cards, int32_t x,
                 int32_t y, const int32_t *z, int32_t nz, int64_t *counts_out, double *g2,
                 int64_t *df, double *p) {
+    return orc_ci_test_ex(data, m, n_vars, cards, x, y, z, nz, ORC_STAT_G2, ORC_DF_DECLARED, counts_out,
+                          g2, df, p);
+}
+
+int orc_ci_test_ex(const uint8_t *data, int64_t m, int32_t n_vars, const uint8_t *cards, int32_t x,
+                   int32_t y, const int32_t *z, int32_t nz, int32_t statistic, int32_t df_rule,
+                   int64_t *counts_out, double *stat_out, int64_t *df, double *p) {
+    if (statistic != ORC_STAT_G2 && statistic != ORC_STAT_X2) return -1;
+    if (df_rule != ORC_DF_DECLARED && df_rule != ORC_DF_ADJUSTED) return -1;
     if (!data || !cards || m < 0 || n_vars <= 0 || nz < 0 || (nz > 0 && !z)) return -1;
     if (x < 0 || x >= n_vars || y < 0 || y >= n_vars || x == y) return -1;
     for (int k = 0; k < nz; ++k)
@@ -123,29 +132,61 @@ int orc_ci_test(const uint8_t *data, int64_t m, int32_t n_vars, const uint8_t *c
                 Nz[zc] += c;
             }
 
-    /* G^2 = 2 sum N ln(N / E), E = N_x+z N_+yz / N_++z, over cells with N > 0
-     * (0 ln 0 = 0).  Both N * N_++z and N_x+z * N_+yz are formed exactly in
-     * int64 (they are below 2^53, so the conversion to double is exact) and
-     * the logarithm is taken of their quotient (step (iii)). */
-    double sum = 0.0;
-    for (int64_t zc = 0; zc < nstrata; ++zc)
-        for (int64_t yv = 0; yv < ry; ++yv)
-            for (int64_t xv = 0; xv < rx; ++xv) {
-                int64_t c = N[xv + rx * (yv + ry * zc)];
-                if (c == 0) continue;
-                int64_t num = c * Nz[zc];
-                int64_t den = Nxz[xv + rx * zc] * Nyz[yv + ry * zc];
-                sum += (double)c * log((double)num / (double)den);
-            }
-    double G2 = 2.0 * sum;
-    if (G2 < 0.0) G2 = 0.0;
+    double G2 = 0.0;
+    if (statistic == ORC_STAT_G2) {
+        /* G^2 = 2 sum N ln(N / E), E = N_x+z N_+yz / N_++z, over cells with N > 0
+         * (0 ln 0 = 0).  Both N * N_++z and N_x+z * N_+yz are formed exactly in
+         * int64 (they are below 2^53, so the conversion to double is exact) and
+         * the logarithm is taken of their quotient (step (iii)). */
+        double sum = 0.0;
+        for (int64_t zc = 0; zc < nstrata; ++zc)
+            for (int64_t yv = 0; yv < ry; ++yv)
+                for (int64_t xv = 0; xv < rx; ++xv) {
+                    int64_t c = N[xv + rx * (yv + ry * zc)];
+                    if (c == 0) continue;
+                    int64_t num = c * Nz[zc];
+                    int64_t den = Nxz[xv + rx * zc] * Nyz[yv + ry * zc];
+                    sum += (double)c * log((double)num / (double)den);
+                }
+        G2 = 2.0 * sum;
+        if (G2 < 0.0) G2 = 0.0;
+    } else {
+        /* Pearson's X^2 = sum (N - E)^2 / E over the cells with E > 0, the
+         * alternative test of Section II on the same table.  E = 0 only when
+         * N_x+z or N_+yz is 0, and then N = 0 too: such cells contribute 0. */
+        double sum = 0.0;
+        for (int64_t zc = 0; zc < nstrata; ++zc)
+            for (int64_t yv = 0; yv < ry; ++yv)
+                for (int64_t xv = 0; xv < rx; ++xv) {
+                    if (Nz[zc] == 0) continue;
+                    double E = (double)Nxz[xv + rx * zc] * (double)Nyz[yv + ry * zc] / (double)Nz[zc];
+                    if (E == 0.0) continue;
+                    double diff = (double)N[xv + rx * (yv + ry * zc)] - E;
+                    sum += diff * diff / E;
+                }
+        G2 = sum;
+    }
 
-    /* df = (r_x - 1)(r_y - 1) prod_k r_{z_k}, from the declared cards. */
-    int64_t dof = (rx - 1) * (ry - 1) * nstrata;
+    int64_t dof;
+    if (df_rule == ORC_DF_DECLARED) {
+        /* df = (r_x - 1)(r_y - 1) prod_k r_{z_k}, from the declared cards. */
+        dof = (rx - 1) * (ry - 1) * nstrata;
+    } else {
+        /* Adjusted df: per non-empty stratum, (rows with N_x+z > 0 minus 1)
+         * times (columns with N_+yz > 0 minus 1); empty strata add nothing. */
+        dof = 0;
+        for (int64_t zc = 0; zc < nstrata; ++zc) {
+            if (Nz[zc] == 0) continue;
+            int64_t a = 0, b = 0;
+            for (int64_t xv = 0; xv < rx; ++xv) a += Nxz[xv + rx * zc] > 0;
+            for (int64_t yv = 0; yv < ry; ++yv) b += Nyz[yv + ry * zc] > 0;
+            dof += (a - 1) * (b - 1);
+        }
+    }
     double pv = (dof == 0) ? 1.0 : orc_gamma_q(0.5 * (double)dof, 0.5 * G2);
 
     if (counts_out) memcpy(counts_out, N, (size_t)T * sizeof(int64_t));
-    if (g2) *g2 = G2;
+    if (stat_out) *stat_out = G2;
     if (df) *df = dof;
     if (p) *p = pv;
     free(N); free(Nxz); free(Nyz); free(Nz);
@@ -177,12 +218,14 @@ typedef struct {
     int32_t n;
     const uint8_t *cards;
     int32_t err;
+    int32_t statistic, df_rule;
 } g2_source;
 
 static double g2_pvalue(void *user, int32_t x, int32_t y, const int32_t *s, int32_t d) {
     g2_source *src = (g2_source *)user;
     double p = 1.0;
-    int rc = orc_ci_test(src->data, src->m, src->n, src->cards, x, y, s, d, NULL, NULL, NULL, &p);
+    int rc = orc_ci_test_ex(src->data, src->m, src->n, src->cards, x, y, s, d, src->statistic,
+                            src->df_rule, NULL, NULL, NULL, &p);
     if (rc != 0 && src->err == 0) src->err = rc;
     return p;
 }
@@ -324,7 +367,12 @@ done:
 
 orc_result *orc_pc_skeleton(const uint8_t *data, int64_t m, int32_t n, const uint8_t *cards,
                             double alpha, int32_t max_depth) {
-    g2_source src = {data, m, n, cards, 0};
+    return orc_pc_skeleton_ex(data, m, n, cards, alpha, max_depth, ORC_STAT_G2, ORC_DF_DECLARED);
+}
+
+orc_result *orc_pc_skeleton_ex(const uint8_t *data, int64_t m, int32_t n, const uint8_t *cards,
+                               double alpha, int32_t max_depth, int32_t statistic, int32_t df_rule) {
+    g2_source src = {data, m, n, cards, 0, statistic, df_rule};
     if (!data || !cards || m <= 0 || n <= 0) {
         orc_result *r = (orc_result *)calloc(1, sizeof(orc_result));
         if (r) r->status = -1;

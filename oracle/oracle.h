@@ -42,6 +42,19 @@ int orc_ci_test(const uint8_t *data, int64_t n_samples, int32_t n_vars, const ui
                 int32_t x, int32_t y, const int32_t *z, int32_t nz, int64_t *counts_out,
                 double *g2, int64_t *df, double *p);
 
+/* Statistic and df rule of orc_ci_test_ex / orc_pc_skeleton_ex. */
+enum { ORC_STAT_G2 = 0, ORC_STAT_X2 = 1 };
+enum { ORC_DF_DECLARED = 0, ORC_DF_ADJUSTED = 1 };
+
+/* orc_ci_test with a choice of statistic (G^2 of Section III-B, or Pearson's
+ * X^2 = sum (N - E)^2 / E over cells with E > 0, named in Section II) and of
+ * degrees of freedom (declared: (r_x - 1)(r_y - 1) prod r_z; adjusted: per
+ * non-empty stratum z, (#x with N_x+z > 0 - 1)(#y with N_+yz > 0 - 1)).
+ * stat_out receives the chosen statistic. */
+int orc_ci_test_ex(const uint8_t *data, int64_t n_samples, int32_t n_vars, const uint8_t *cards,
+                   int32_t x, int32_t y, const int32_t *z, int32_t nz, int32_t statistic,
+                   int32_t df_rule, int64_t *counts_out, double *stat_out, int64_t *df, double *p);
+
 /* A CI decision source for the PC-stable driver: returns a p-value for
  * I(x, y | s[0..d)); the driver declares independence when p > alpha. */
 typedef double (*orc_ci_fn)(void *user, int32_t x, int32_t y, const int32_t *s, int32_t d);
@@ -51,6 +64,11 @@ typedef struct orc_result orc_result;
 /* PC-stable step 1 with the G^2 test on the data.  max_depth < 0: unbounded. */
 orc_result *orc_pc_skeleton(const uint8_t *data, int64_t n_samples, int32_t n_vars,
                             const uint8_t *cards, double alpha, int32_t max_depth);
+
+/* Same, with the statistic and df rule of orc_ci_test_ex. */
+orc_result *orc_pc_skeleton_ex(const uint8_t *data, int64_t n_samples, int32_t n_vars,
+                               const uint8_t *cards, double alpha, int32_t max_depth,
+                               int32_t statistic, int32_t df_rule);
 
 /* PC-stable step 1 with an arbitrary CI decision source (used to check the
  * driver against a d-separation oracle). */

@@ -14,11 +14,12 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.c")
-PINS = ["tests/test_oracle_ci.py", "tests/test_oracle_pvalue.py", "tests/test_oracle_pc.py"]
+PINS = ["tests/test_oracle_ci.py", "tests/test_oracle_pvalue.py", "tests/test_oracle_pc.py",
+        "tests/test_oracle_stats.py"]
 
 MUTANTS = {
     "transposed_cell_index": ("N[cx[s] + rx * (cy[s] + ry * zc)]", "N[cx[s] + ry * (cy[s] + rx * zc)]"),
-    "dropped_factor_two": ("double G2 = 2.0 * sum;", "double G2 = sum;"),
+    "dropped_factor_two": ("G2 = 2.0 * sum;", "G2 = sum;"),
     "inverted_log_ratio": ("log((double)num / (double)den)", "log((double)den / (double)num)"),
     "df_without_strata": ("(rx - 1) * (ry - 1) * nstrata;", "(rx - 1) * (ry - 1);"),
     "tie_counts_as_independent": ("if (pv > alpha) {", "if (pv >= alpha) {"),
@@ -35,6 +36,11 @@ MUTANTS = {
     "z_radix_wrong": ("mult *= cards[z[k]];", "mult *= rx;"),
     "knife_edges_never_counted": ("if (gap < 1e-9) r->knife += 1;", "if (gap < 0.0) r->knife += 1;"),
     "gap_measured_on_complement": ("double gap = fabs(pv - alpha);", "double gap = fabs((1.0 - pv) - alpha);"),
+    "x2_not_squared": ("sum += diff * diff / E;", "sum += fabs(diff) / E;"),
+    "x2_smoothed_expectation": ("sum += diff * diff / E;", "sum += diff * diff / (E + 0.5);"),
+    "adjusted_df_keeps_empty_rows": ("a += Nxz[xv + rx * zc] > 0;", "a += 1;"),
+    "adjusted_df_counts_empty_strata": ("            if (Nz[zc] == 0) continue;\n            int64_t a = 0, b = 0;",
+                                        "            int64_t a = 0, b = 0;"),
 }
 
 
