@@ -125,8 +125,9 @@ struct CiOutDev {
 struct Tile {
     int32_t lds_words;     // dynamic LDS per workgroup, in 32-bit words
     int32_t max_rep_log2;  // cap on per-table replication (log2)
-    int32_t fp64;          // 1: FP64 G^2; 0: FP32 + FP64 recheck
-    int32_t pad;
+    int32_t fp64;          // 1: FP64 statistic; 0: FP32 + FP64 recheck
+    int16_t stat;          // 0: G^2; 1: Pearson X^2
+    int16_t df_rule;       // 0: df from the declared cards; 1: adjusted for empty rows, columns, strata
     double band;           // recheck band on |p - alpha|
 };
 

@@ -102,8 +102,8 @@ static bns_status read_options(const bns_options *in, bns_options *out) {
         return fail(BNS_E_INVALID_ARG, "options.depth0 must be a BNS_DEPTH0_* value");
     for (int i = 0; i < 3; ++i)
         if (out->reserved[i] != 0) return fail(BNS_E_INVALID_ARG, "options.reserved must be zero");
-    if (out->statistic != BNS_STAT_G2 || out->df_rule != BNS_DF_DECLARED || out->depth0 == BNS_DEPTH0_PAIRS)
-        return fail(BNS_E_INVALID_ARG, "options.statistic, df_rule and depth0 = PAIRS are not available yet");
+    if (out->depth0 == BNS_DEPTH0_PAIRS)
+        return fail(BNS_E_INVALID_ARG, "options.depth0 = BNS_DEPTH0_PAIRS is not available yet");
     return BNS_OK;
 }
 
@@ -394,7 +394,8 @@ static bns_status make_tile_for(int max_lds_block, int default_lds, const bns_op
     if (o.max_replicas > 0) t->max_rep_log2 = __builtin_ctz((unsigned)o.max_replicas);
     t->fp64 = (o.precision == BNS_PREC_FP64) ? 1 : 0;
     t->band = o.recheck_band;
-    t->pad = 0;
+    t->stat = (int16_t)o.statistic;
+    t->df_rule = (int16_t)o.df_rule;
     return BNS_OK;
 }
 
@@ -1214,7 +1215,8 @@ static bns_status plain_test(DevCtx &dc, const bns_dataset *ds, const Tile &tile
     HIP_TRY(launch_plain_count(ds->d_data, ds->ld, ds->m, ds->d_cards, pt, spb, nblocks,
                                dc.plain_part.as<uint32_t>(), T, tile.lds_words, s));
     HIP_TRY(launch_plain_finish(ds->d_cards, pt, nblocks, dc.plain_part.as<uint32_t>(), T,
-                                dc.plain_ws.as<uint32_t>(), alpha, dc.plain_out.as<CiOutDev>(), s));
+                                dc.plain_ws.as<uint32_t>(), alpha, tile.stat, tile.df_rule,
+                                dc.plain_out.as<CiOutDev>(), s));
     HIP_TRY(hipMemcpyAsync(dc.h_out, dc.plain_out.p, sizeof(CiOutDev), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     *res = *dc.h_out;

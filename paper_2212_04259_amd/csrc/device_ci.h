@@ -313,6 +313,31 @@ BNS_INLINE float g2_half_term<float>(uint32_t N, uint32_t nxz, uint32_t nyz, uin
 }
 
 // ---------------------------------------------------------------------------
+// One cell's Pearson term (N - E)^2 / E (the alternative statistic of Section
+// II on the same table), E = N_x+z N_+yz / N_++z, written with a = N N_++z and
+// b = N_x+z N_+yz (exact integers) as (a - b)^2 / (N_++z b).  Cells with E = 0
+// (then also N = 0) contribute 0.  Every term is non-negative.
+// ---------------------------------------------------------------------------
+template <typename Real>
+BNS_INLINE Real x2_term(uint32_t N, uint32_t nxz, uint32_t nyz, uint32_t nzz) {
+    const uint64_t b = (uint64_t)nxz * nyz;
+    if (b == 0) return (Real)0;
+    const uint64_t a = (uint64_t)N * nzz;
+    const double dd = (double)((int64_t)a - (int64_t)b);  // exact below 2^53
+    const Real d = (Real)dd;
+    return (d / (Real)b) * (d / (Real)nzz);
+}
+
+template <>
+BNS_INLINE float x2_term<float>(uint32_t N, uint32_t nxz, uint32_t nyz, uint32_t nzz) {
+    const uint64_t b = (uint64_t)nxz * nyz;
+    if (b == 0) return 0.0f;
+    const uint64_t a = (uint64_t)N * nzz;
+    const float d = (float)(double)((int64_t)a - (int64_t)b);
+    return (d * __builtin_amdgcn_rcpf((float)b)) * (d * __builtin_amdgcn_rcpf((float)nzz));
+}
+
+// ---------------------------------------------------------------------------
 // Counting (step (i) of Section IV-A) into an LDS table.
 //
 // Columns are uint8, read 16 samples per lane per column with coalesced
@@ -609,12 +634,13 @@ BNS_INLINE void marginals(const Grp &g, const uint32_t *tab, uint32_t *rows, uin
     g.sync();
 }
 
-// This lane's part of the sum of g2_half_term over a chunk: one cell per
-// lane and step (a table with no more cells than lanes costs one term).
+// This lane's part of the sum of the statistic's cell terms over a chunk
+// (g2_half_term for G^2, stat 0; x2_term for X^2, stat 1): one cell per lane
+// and step (a table with no more cells than lanes costs one term).
 template <typename Real>
-BNS_INLINE Real g2_partial(const Grp &g, const uint32_t *tab, const uint32_t *rows,
-                           const uint32_t *cols, const uint32_t *strata, uint32_t rx, uint32_t ry,
-                           uint32_t Zc) {
+BNS_INLINE Real stat_partial(const Grp &g, const uint32_t *tab, const uint32_t *rows,
+                             const uint32_t *cols, const uint32_t *strata, uint32_t rx, uint32_t ry,
+                             uint32_t Zc, int stat) {
     const float inv_rx = 1.0f / (float)rx, inv_ry = 1.0f / (float)ry;
     const uint32_t T = rx * ry * Zc;
     Real acc = 0;
@@ -624,7 +650,23 @@ BNS_INLINE Real g2_partial(const Grp &g, const uint32_t *tab, const uint32_t *ro
         const uint32_t z = fast_div(rho, ry, inv_ry);
         const uint32_t nzz = strata[z];
         if (nzz == 0) continue;
-        acc += g2_half_term<Real>(tab[c], rows[xv + rx * z], cols[rho], nzz);
+        if (stat) acc += x2_term<Real>(tab[c], rows[xv + rx * z], cols[rho], nzz);
+        else acc += g2_half_term<Real>(tab[c], rows[xv + rx * z], cols[rho], nzz);
+    }
+    return acc;
+}
+
+// This lane's part of the adjusted degrees of freedom of a chunk of strata:
+// per stratum with N_++z > 0, (non-empty rows - 1)(non-empty columns - 1).
+BNS_INLINE double adj_df_partial(const Grp &g, const uint32_t *rows, const uint32_t *cols,
+                                 const uint32_t *strata, uint32_t rx, uint32_t ry, uint32_t Zc) {
+    double acc = 0.0;
+    for (uint32_t z = g.rank; z < Zc; z += g.size) {
+        if (strata[z] == 0) continue;
+        uint32_t a = 0, b = 0;
+        for (uint32_t xv = 0; xv < rx; ++xv) a += rows[xv + rx * z] > 0u ? 1u : 0u;
+        for (uint32_t yv = 0; yv < ry; ++yv) b += cols[yv + ry * z] > 0u ? 1u : 0u;
+        acc += (double)(a - 1u) * (double)(b - 1u);
     }
     return acc;
 }
@@ -716,9 +758,12 @@ struct Src {
 // replication); with src.gdst the counts of samples [s0, s1) are added to
 // src.gdst with device-scope atomics (non-zero cells only) and nothing else
 // is computed.
+// The statistic is G^2 (stat 0) or X^2 (stat 1); with df_adj the adjusted
+// degrees of freedom of the table are summed into *df_adj.
 BNS_INLINE double table_pass(const Grp &g, TestSh &t, const Plan &P, uint32_t *lds, uint32_t *gtab,
-                             const Src &src, bool fp64, const uint32_t **tab_out) {
-    double part64 = 0.0;
+                             const Src &src, bool fp64, const uint32_t **tab_out, int stat,
+                             double *df_adj) {
+    double part64 = 0.0, dfp = 0.0;
     float part32 = 0.0f;
     const uint32_t *tab = lds;
     const bool chunked = P.nchunks > 1;
@@ -786,25 +831,28 @@ BNS_INLINE double table_pass(const Grp &g, TestSh &t, const Plan &P, uint32_t *l
         if (gtab)
             for (uint32_t i = g.rank; i < Tc; i += g.size) gtab[P.rxy * z0 + i] = red[i];
         marginals(g, red, rows, cols, strata, P.rx, P.ry, Zc);
-        if (fp64) part64 += g2_partial<double>(g, red, rows, cols, strata, P.rx, P.ry, Zc);
-        else part32 += g2_partial<float>(g, red, rows, cols, strata, P.rx, P.ry, Zc);
+        if (fp64) part64 += stat_partial<double>(g, red, rows, cols, strata, P.rx, P.ry, Zc, stat);
+        else part32 += stat_partial<float>(g, red, rows, cols, strata, P.rx, P.ry, Zc, stat);
+        if (df_adj) dfp += adj_df_partial(g, rows, cols, strata, P.rx, P.ry, Zc);
         tab = red;
         if (c + 1 < P.nchunks) g.sync();
     }
     *tab_out = tab;
     if (src.gdst) return 0.0;
-    if (fp64) return 2.0 * g.sum(part64, t);
-    return 2.0 * (double)g.sum(part32, t);
+    if (df_adj) *df_adj = g.sum(dfp, t);
+    const double scale = stat ? 1.0 : 2.0;  // G^2 = 2 sum of the half terms
+    if (fp64) return scale * g.sum(part64, t);
+    return scale * (double)g.sum(part32, t);
 }
 
-// FP64 G^2 from a single-pass table and marginals still resident in LDS.
-BNS_INLINE double g2_fp64_resident(const Grp &g, TestSh &t, const Plan &P, const uint32_t *tab) {
+// FP64 statistic from a single-pass table and marginals still resident in LDS.
+BNS_INLINE double stat_fp64_resident(const Grp &g, TestSh &t, const Plan &P, const uint32_t *tab, int stat) {
     const uint32_t Zc = P.nstrata;
     const uint32_t *rows = tab + P.rxy * Zc;
     const uint32_t *cols = rows + P.rx * Zc;
     const uint32_t *strata = cols + P.ry * Zc;
-    const double part = g2_partial<double>(g, tab, rows, cols, strata, P.rx, P.ry, Zc);
-    return 2.0 * g.sum(part, t);
+    const double part = stat_partial<double>(g, tab, rows, cols, strata, P.rx, P.ry, Zc, stat);
+    return (stat ? 1.0 : 2.0) * g.sum(part, t);
 }
 
 // Relative error bound of the FP32 G^2 sum: every summand is non-negative and
@@ -841,7 +889,9 @@ BNS_INLINE Tail group_tail(const Grp &g, int64_t df, double g2, TestSh &t) {
 // gtab (may be null) receives the exact table.  src: the samples counted, or
 // the merged table of a split test to evaluate, or a merge target (then only
 // the chunk [s0, s1) is counted and added there; no G^2, no decision).
-template <bool kVerify = false>
+// kGeneral: the statistic and df rule come from the tile; otherwise the
+// instance is fixed to G^2 with df from the declared cards.
+template <bool kVerify = false, bool kGeneral = true>
 BNS_INLINE TestOut run_test(const Grp &g, TestSh &t, uint32_t *lds, uint32_t W, const Tile &tile,
                             double alpha, uint32_t *gtab, const Src &src) {
     TestOut o;
@@ -865,23 +915,29 @@ BNS_INLINE TestOut run_test(const Grp &g, TestSh &t, uint32_t *lds, uint32_t W, 
     // fitted in one pass, otherwise by a second counting pass.
     const uint32_t *tab = nullptr;
     bool fp64 = tile.fp64 != 0;
+    const int stat = kGeneral ? tile.stat : 0;
+    const bool adj = kGeneral && tile.df_rule != 0;
     double g2 = 0.0, p = 1.0, p_first = 1.0;
+    int64_t df = P.df;
     for (int round = 0; round < 2; ++round) {
-        g2 = table_pass(g, t, P, lds, round == 0 ? gtab : nullptr, src, fp64, &tab);
+        double dfa = 0.0;
+        g2 = table_pass(g, t, P, lds, round == 0 ? gtab : nullptr, src, fp64, &tab, stat,
+                        adj ? &dfa : nullptr);
         if (src.gdst) {  // merge only: no statistic, no decision
             o.g2 = 0.0;
             o.p = 1.0;
             return o;
         }
-        Tail tl = group_tail(g, P.df, g2, t);
+        if (adj) df = (int64_t)dfa;
+        Tail tl = group_tail(g, df, g2, t);
         p = tl.p;
         if (round == 0) {
             o.g2_first = g2;
             p_first = p;
         }
-        if (fp64 || P.df <= 0) break;
+        if (fp64 || df <= 0) break;
         const double gap = fabs(p - alpha);
-        // propagate the FP32 error bound of G^2 through the tail's slope
+        // propagate the FP32 error bound of the statistic through the tail's slope
         const double dp = tl.dens * 0.5 * g2 * fp32_g2_rel_bound(P, g.size);
         if (!(gap < tile.band || gap < 4.0 * dp)) break;
         o.flags |= 2;
@@ -889,10 +945,11 @@ BNS_INLINE TestOut run_test(const Grp &g, TestSh &t, uint32_t *lds, uint32_t W, 
             fp64 = true;
             continue;
         }
-        g2 = g2_fp64_resident(g, t, P, tab);
-        p = group_tail(g, P.df, g2, t).p;
+        g2 = stat_fp64_resident(g, t, P, tab, stat);
+        p = group_tail(g, df, g2, t).p;
         break;
     }
+    o.df = df;
     o.g2 = g2;
     o.p = p;
     if (p > alpha) o.flags |= 1;
@@ -900,10 +957,10 @@ BNS_INLINE TestOut run_test(const Grp &g, TestSh &t, uint32_t *lds, uint32_t W, 
         // FP64 value of the statistic: the decision's own when it was FP64,
         // else from the table still in LDS (one pass) or by counting again.
         double g64 = g2, p64 = p;
-        if (!fp64 && !(o.flags & 2) && P.df > 0) {
-            if (P.nchunks == 1) g64 = g2_fp64_resident(g, t, P, tab);
-            else g64 = table_pass(g, t, P, lds, nullptr, src, true, &tab);
-            p64 = group_tail(g, P.df, g64, t).p;
+        if (!fp64 && !(o.flags & 2) && df > 0) {
+            if (P.nchunks == 1) g64 = stat_fp64_resident(g, t, P, tab, stat);
+            else g64 = table_pass(g, t, P, lds, nullptr, src, true, &tab, stat, nullptr);
+            p64 = group_tail(g, df, g64, t).p;
         }
         o.g2_ref = g64;
         o.flip = ((p_first > alpha) != (p64 > alpha)) ? 1 : 0;

@@ -121,7 +121,7 @@ hipError_t launch_plain_count(const uint8_t *data, int64_t ld, int64_t m, const 
                               uint32_t *partials, int64_t T, int lds_words, hipStream_t s);
 hipError_t launch_plain_finish(const uint8_t *cards, const PlainTest &t, int nblocks,
                                const uint32_t *partials, int64_t T, uint32_t *table_ws,
-                               double alpha, CiOutDev *out, hipStream_t s);
+                               double alpha, int stat, int df_rule, CiOutDev *out, hipStream_t s);
 
 // Checks every value against its cardinality; first offending flat index
 // (v * m + s) is atomically minimised into *bad (initialised to INT64_MAX).

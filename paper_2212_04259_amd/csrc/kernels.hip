@@ -997,7 +997,9 @@ struct Batch {
 // single units keeps the shortest arithmetic).
 // VERIFY: the verification instance (every test also evaluated in FP64 and
 // its FP32 error logged); the timed searches use the other.
-template <int LGB, bool VERIFY>
+// GENERAL: the instance for other statistics or df rules than G^2 with the
+// declared df.
+template <int LGB, bool VERIFY, bool GENERAL>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k_depth_tests(DepthArgs A) {
     extern __shared__ uint32_t lds[];
     __shared__ TestSh tsh[kWaves];
@@ -1154,7 +1156,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
                 }
             }
             for (;;) {
-                const TestOut o = run_test<VERIFY>(g, t, region, W, A.tile, uni(q.alpha), nullptr, src);
+                const TestOut o = run_test<VERIFY, GENERAL>(g, t, region, W, A.tile, uni(q.alpha), nullptr, src);
                 if (g.rank == 0) tal_bytes[ti] += (double)q.ncols * (double)(src.s1 - src.s0);
                 if (src.gdst) {
                     // Every access to a merge table and its chunk counter is
@@ -1580,9 +1582,13 @@ hipError_t launch_depth_prepare(const DepthArgs &a, hipStream_t s) {
 
 // Instance for the search: tickets dealt in runs when its columns exceed the
 // last-level cache's share (grab_block_log2 = kGrabRunLog2), else singly.
-static auto depth_tests_kernel(const DepthArgs &a) -> decltype(&k_depth_tests<0, false>) {
-    if (a.err_val) return &k_depth_tests<0, true>;  // verification (the dealing of tickets is irrelevant)
-    return a.grab_block_log2 ? &k_depth_tests<kGrabRunLog2, false> : &k_depth_tests<0, false>;
+static auto depth_tests_kernel(const DepthArgs &a) -> decltype(&k_depth_tests<0, false, false>) {
+    const bool general = a.tile.stat != 0 || a.tile.df_rule != 0;
+    // verification and other statistics: single-ticket dealing (the dealing
+    // never changes results)
+    if (a.err_val) return general ? &k_depth_tests<0, true, true> : &k_depth_tests<0, true, false>;
+    if (general) return &k_depth_tests<0, false, true>;
+    return a.grab_block_log2 ? &k_depth_tests<kGrabRunLog2, false, false> : &k_depth_tests<0, false, false>;
 }
 
 hipError_t launch_depth_tests(const DepthArgs &a, int grid, hipStream_t s, hipEvent_t start,
@@ -1602,14 +1608,12 @@ hipError_t launch_depth_apply(const DepthArgs &a, hipStream_t s) {
 }
 
 hipError_t allow_dynamic_lds(int bytes) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_depth_tests<kGrabRunLog2, false>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_depth_tests<0, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                bytes);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_depth_tests<0, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                bytes);
+    const void *fns[] = {(const void *)k_depth_tests<kGrabRunLog2, false, false>,
+                         (const void *)k_depth_tests<0, false, false>, (const void *)k_depth_tests<0, true, false>,
+                         (const void *)k_depth_tests<0, false, true>, (const void *)k_depth_tests<0, true, true>};
+    hipError_t e = hipSuccess;
+    for (const void *f : fns)
+        if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void *)k_ci_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 bytes);
@@ -1621,7 +1625,7 @@ hipError_t allow_dynamic_lds(int bytes) {
 
 int depth_tests_max_wg_per_cu(int lds_bytes) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_depth_tests<0, false>, kWG, (size_t)lds_bytes) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_depth_tests<0, false, false>, kWG, (size_t)lds_bytes) !=
         hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
@@ -1635,7 +1639,7 @@ int depth_tests_fit_lds(int lds_per_cu) {
     const int target = depth_tests_max_wg_per_cu(4096);
     hipFuncAttributes fa;
     int stat = 16384;
-    if (hipFuncGetAttributes(&fa, (const void *)k_depth_tests<0, false>) == hipSuccess) stat = (int)fa.sharedSizeBytes;
+    if (hipFuncGetAttributes(&fa, (const void *)k_depth_tests<0, false, false>) == hipSuccess) stat = (int)fa.sharedSizeBytes;
     if (lds_per_cu <= 0) lds_per_cu = 65536;
     const int share = (lds_per_cu / max(target, 1)) & ~2047;
     int b = (share - stat) & ~255;
@@ -1770,7 +1774,7 @@ __global__ __launch_bounds__(kWG) void k_plain_count(const uint8_t *data, int64_
 __global__ __launch_bounds__(kWG) void k_plain_finish(const uint8_t *cards, const PlainTest pt,
                                                       int nblocks, const uint32_t *partials,
                                                       int64_t T, uint32_t *ws, double alpha,
-                                                      CiOutDev *out) {
+                                                      int stat, int df_rule, CiOutDev *out) {
     __shared__ TestSh t;
     const uint32_t rx = cards[pt.vars[0]], ry = cards[pt.vars[1]];
     uint32_t Z = 1;
@@ -1784,9 +1788,10 @@ __global__ __launch_bounds__(kWG) void k_plain_finish(const uint8_t *cards, cons
     uint32_t *rows = ws + T, *cols = rows + rx * Z, *strata = cols + ry * Z;
     const Grp gb = Grp::workgroup();
     marginals(gb, ws, rows, cols, strata, rx, ry, Z);
-    const double part = g2_partial<double>(gb, ws, rows, cols, strata, rx, ry, Z);
-    const double g2 = 2.0 * gb.sum(part, t);
-    const int64_t df = (int64_t)(rx - 1) * (int64_t)(ry - 1) * (int64_t)Z;
+    const double part = stat_partial<double>(gb, ws, rows, cols, strata, rx, ry, Z, stat);
+    const double g2 = (stat ? 1.0 : 2.0) * gb.sum(part, t);
+    int64_t df = (int64_t)(rx - 1) * (int64_t)(ry - 1) * (int64_t)Z;
+    if (df_rule) df = (int64_t)gb.sum(adj_df_partial(gb, rows, cols, strata, rx, ry, Z), t);
     const double p = group_tail(gb, df, g2, t).p;
     if (threadIdx.x == 0) {
         CiOutDev r;
@@ -1809,9 +1814,9 @@ hipError_t launch_plain_count(const uint8_t *data, int64_t ld, int64_t m, const 
 
 hipError_t launch_plain_finish(const uint8_t *cards, const PlainTest &t, int nblocks,
                                const uint32_t *partials, int64_t T, uint32_t *ws, double alpha,
-                               CiOutDev *out, hipStream_t s) {
+                               int stat, int df_rule, CiOutDev *out, hipStream_t s) {
     hipLaunchKernelGGL(k_plain_finish, dim3(1), dim3(kWG), 0, s, cards, t, nblocks, partials, T, ws,
-                       alpha, out);
+                       alpha, stat, df_rule, out);
     return hipGetLastError();
 }
 
