@@ -72,3 +72,35 @@ def test_mutant_is_caught(tmp_path, name):
 def test_unmodified_source_passes(tmp_path):
     so = _build(tmp_path, open(SRC).read(), "clean")
     assert _run_pins(so) == 0
+
+
+# Mistakes planted in copies of the orientation oracle (oracle/orient.py),
+# caught by tests/test_oracle_orient.py.
+ORIENT_SRC = os.path.join(ROOT, "oracle", "orient.py")
+ORIENT_MUTANTS = {
+    "collider_when_in_sepset": ("if z not in sepsets[(min(x, y), max(x, y))]:",
+                                "if z in sepsets[(min(x, y), max(x, y))]:"),
+    "triples_ignore_adjacency": ("                if adj[x, y]:\n                    continue\n", ""),
+    "r1_without_nonadjacency": ("if any(_directed(G, c, a) and not adj[c, b] for c in range(n) if c not in (a, b)):",
+                                "if any(_directed(G, c, a) for c in range(n) if c not in (a, b)):"),
+    "r2_reversed": ("if any(_directed(G, a, c) and _directed(G, c, b) for c in range(n) if c not in (a, b)):",
+                    "if any(_directed(G, c, a) and _directed(G, b, c) for c in range(n) if c not in (a, b)):"),
+    "r3_dropped": ("            if any(not adj[c, d] for i, c in enumerate(cs) for d in cs[i + 1:]):\n"
+                   "                found.add((a, b))\n", ""),
+    "conflict_resolved_by_order": ("            if (b, a) not in found:\n                G[b, a] = 1",
+                                   "            G[b, a] = 1"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(ORIENT_MUTANTS))
+def test_orient_mutant_is_caught(tmp_path, name):
+    src = open(ORIENT_SRC).read()
+    old, new = ORIENT_MUTANTS[name]
+    assert src.count(old) == 1, f"mutation anchor for {name} not found exactly once"
+    path = tmp_path / "orient_mut.py"
+    path.write_text(src.replace(old, new))
+    env = dict(os.environ, BNS_ORIENT_SRC=str(path))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        "tests/test_oracle_orient.py"], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode != 0, f"pins did not catch orientation mutant {name}"
