@@ -323,6 +323,32 @@ bns_status bns_skeleton_removals(const bns_skeleton *sk, int32_t *depth, int64_t
 bns_status bns_skeleton_stats(const bns_skeleton *sk, bns_depth_stats *out, int32_t cap,
                               int32_t *n_depths);
 
+/* A skeleton handle from host arrays (e.g. to orient a skeleton learned
+ * elsewhere): adj (n * n uint8, symmetric, 0/1, zero diagonal), depth (n * n
+ * int32: removal depth of each removed pair, -1 for kept edges, symmetric),
+ * sep_off (n * n int64: for a pair removed at depth d >= 1, the offset of its
+ * d sepset members in pool, ascending ids other than the pair; unused
+ * otherwise).  The arrays are copied; inconsistent input gives
+ * BNS_E_INVALID_ARG.  No device work; the handle has no per-depth counters. */
+bns_status bns_skeleton_create(int32_t n_vars, const uint8_t *adj, const int32_t *depth,
+                               const int64_t *sep_off, const int32_t *pool, int64_t pool_len,
+                               bns_skeleton **out);
+
+/* PC steps 2 and 3 (Section III-C) on a learned skeleton: its CPDAG.
+ * Step 2 orients x -> z <- y for every unshielded triple x - z - y (x and y
+ * not adjacent) whose middle node z is not in SepSet(x, y); every triple is
+ * judged on the skeleton, so the result does not depend on their order, and an
+ * edge that two triples orient both ways keeps arrowheads at both ends (a
+ * conflict).  Step 3 applies Meek's rules R1-R3 to the undirected edges, with
+ * singly-directed edges as premises, in rounds: the orientations a round
+ * implies are all found on the graph as it stood and then applied together;
+ * an edge one round orients both ways keeps both arrowheads.  cpdag (n_vars *
+ * n_vars int8, caller-allocated): cpdag[i * n + j] = 0 when i and j are not
+ * adjacent, 1 when they are and the edge has no arrowhead at j, 2 when it has
+ * one at j: i -> j is 2 / 1, an undirected edge 1 / 1, a conflict 2 / 2.
+ * Runs on the host; the handle is not modified. */
+bns_status bns_skeleton_orient(const bns_skeleton *sk, int8_t *cpdag);
+
 void bns_skeleton_free(bns_skeleton *sk);
 
 #ifdef __cplusplus

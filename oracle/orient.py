@@ -1,6 +1,7 @@
 """Oracle of PC steps 2 and 3: orientation of a learned skeleton into a CPDAG.
 
-TEST INFRASTRUCTURE ONLY: a plain, slow, pure-Python reference.  Only the test
+TEST INFRASTRUCTURE ONLY: a plain, slow Python reference (numpy boolean vectors
+for the premises over a third node).  Only the test
 suite may use it; the product library never does, and it shares no code with
 the library's orientation.
 
@@ -56,33 +57,31 @@ def v_structures(adj, sepsets):
     return G
 
 
-def _directed(G, a, b):
-    return G[a, b] == 2 and G[b, a] == 1
-
-
-def _undirected(G, a, b):
-    return G[a, b] == 1 and G[b, a] == 1
-
-
 def meek_round(G):
-    """Orientations (a, b) meaning a -> b implied by R1-R3 on G."""
+    """Orientations (a, b) meaning a -> b implied by R1-R3 on G.  The
+    premises over the third node c are boolean vectors over all nodes:
+    D[c, a] is "c -> a", U[a, c] is "a - c"."""
     n = G.shape[0]
     adj = G > 0
+    D = (G == 2) & (G.T == 1)
+    U = (G == 1) & (G.T == 1)
     found = set()
     for a in range(n):
         for b in range(n):
-            if a == b or not _undirected(G, a, b):
+            if a == b or not U[a, b]:
                 continue
             # R1: some c -> a with c, b not adjacent orients a -> b
-            if any(_directed(G, c, a) and not adj[c, b] for c in range(n) if c not in (a, b)):
+            r1 = D[:, a] & ~adj[:, b]
+            r1[b] = False
+            if r1.any():
                 found.add((a, b))
                 continue
             # R2: a -> c -> b orients a -> b
-            if any(_directed(G, a, c) and _directed(G, c, b) for c in range(n) if c not in (a, b)):
+            if (D[a, :] & D[:, b]).any():
                 found.add((a, b))
                 continue
             # R3: a - c -> b and a - d -> b with c, d not adjacent orients a -> b
-            cs = [c for c in range(n) if c not in (a, b) and _undirected(G, a, c) and _directed(G, c, b)]
+            cs = np.flatnonzero(U[a, :] & D[:, b])
             if any(not adj[c, d] for i, c in enumerate(cs) for d in cs[i + 1:]):
                 found.add((a, b))
     return found

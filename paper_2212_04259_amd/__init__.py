@@ -32,6 +32,7 @@ from ._lib import (  # noqa: F401
     bns_dataset_wrap_device,
     bns_options,
     bns_options_default,
+    bns_orient,
     bns_pc_skeleton,
     bns_pc_skeleton_batch,
     bns_pc_skeleton_dataset,

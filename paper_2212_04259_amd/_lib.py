@@ -34,7 +34,7 @@ EXPORTS = [
     "bns_dataset_free", "bns_ci_batch", "bns_pc_skeleton", "bns_pc_skeleton_dataset",
     "bns_pc_skeleton_batch", "bns_skeleton_n_vars", "bns_skeleton_adjacency",
     "bns_skeleton_sepset", "bns_skeleton_removals", "bns_skeleton_stats", "bns_skeleton_free",
-    "bns_autotune", "bns_ci_batch_noalloc",
+    "bns_autotune", "bns_ci_batch_noalloc", "bns_skeleton_orient", "bns_skeleton_create",
 ]
 NOALLOC_SCRATCH_BYTES = 16 << 20
 
@@ -127,6 +127,10 @@ def load():
     L.bns_skeleton_removals.argtypes = [vp, vp, vp, vp, i64, P(i64)]
     L.bns_skeleton_stats.restype = i32
     L.bns_skeleton_stats.argtypes = [vp, P(bns_depth_stats), i32, P(i32)]
+    L.bns_skeleton_create.restype = i32
+    L.bns_skeleton_create.argtypes = [i32, vp, vp, vp, vp, i64, P(vp)]
+    L.bns_skeleton_orient.restype = i32
+    L.bns_skeleton_orient.argtypes = [vp, vp]
     L.bns_skeleton_free.restype = None
     L.bns_skeleton_free.argtypes = [vp]
     _lib = L
@@ -247,13 +251,14 @@ class Skeleton:
     depth: np.ndarray
     sepsets: dict
     stats: list = field(default_factory=list)
+    cpdag: np.ndarray | None = None   # int8 marks of bns_skeleton_orient (when asked for)
 
     def edges(self):
         n = self.adj.shape[0]
         return [(i, j) for i in range(n) for j in range(i + 1, n) if self.adj[i, j]]
 
 
-def _collect(h) -> Skeleton:
+def _collect(h, orient: bool = False) -> Skeleton:
     L = load()
     try:
         n = L.bns_skeleton_n_vars(h)
@@ -275,29 +280,33 @@ def _collect(h) -> Skeleton:
         st = (bns_depth_stats * max(nd.value, 1))()
         _check(L.bns_skeleton_stats(h, st, nd.value, ctypes.byref(nd)))
         stats = [{f: getattr(st[d], f) for f, _ in bns_depth_stats._fields_} for d in range(nd.value)]
-        return Skeleton(adj=adj, depth=depth, sepsets=sep, stats=stats)
+        cp = None
+        if orient:
+            cp = np.zeros((n, n), dtype=np.int8)
+            _check(L.bns_skeleton_orient(h, _ptr(cp)))
+        return Skeleton(adj=adj, depth=depth, sepsets=sep, stats=stats, cpdag=cp)
     finally:
         L.bns_skeleton_free(h)
 
 
 def bns_pc_skeleton(data: np.ndarray, cards: np.ndarray, alpha: float = 0.05, max_depth: int = -1,
-                    options: bns_options | None = None) -> Skeleton:
+                    options: bns_options | None = None, orient: bool = False) -> Skeleton:
     data = np.ascontiguousarray(data, dtype=np.uint8)
     cards = np.ascontiguousarray(cards, dtype=np.uint8)
     o = options if options is not None else bns_options_default()
     h = ctypes.c_void_p()
     _check(load().bns_pc_skeleton(_ptr(data), data.shape[1], data.shape[0], _ptr(cards),
                                   float(alpha), int(max_depth), ctypes.byref(o), ctypes.byref(h)))
-    return _collect(h)
+    return _collect(h, orient)
 
 
 def bns_pc_skeleton_dataset(ds: Dataset, alpha: float = 0.05, max_depth: int = -1,
-                            options: bns_options | None = None) -> Skeleton:
+                            options: bns_options | None = None, orient: bool = False) -> Skeleton:
     o = options if options is not None else bns_options_default()
     h = ctypes.c_void_p()
     _check(load().bns_pc_skeleton_dataset(ds.handle, float(alpha), int(max_depth),
                                           ctypes.byref(o), ctypes.byref(h)))
-    return _collect(h)
+    return _collect(h, orient)
 
 
 def bns_autotune(datasets, alphas, max_depths, base: bns_options | None = None,
@@ -315,7 +324,8 @@ def bns_autotune(datasets, alphas, max_depths, base: bns_options | None = None,
     return out
 
 
-def bns_pc_skeleton_batch(datasets, alphas, max_depths, options: bns_options | None = None):
+def bns_pc_skeleton_batch(datasets, alphas, max_depths, options: bns_options | None = None,
+                          orient: bool = False):
     k = len(datasets)
     hs = (ctypes.c_void_p * k)(*[d.handle for d in datasets])
     al = np.ascontiguousarray(alphas, dtype=np.float64)
@@ -324,7 +334,7 @@ def bns_pc_skeleton_batch(datasets, alphas, max_depths, options: bns_options | N
     o = options if options is not None else bns_options_default()
     _check(load().bns_pc_skeleton_batch(ctypes.cast(hs, ctypes.c_void_p), k, _ptr(al), _ptr(md),
                                         ctypes.byref(o), ctypes.cast(outs, ctypes.c_void_p)))
-    return [_collect(ctypes.c_void_p(outs[i])) for i in range(k)]
+    return [_collect(ctypes.c_void_p(outs[i]), orient) for i in range(k)]
 
 
 def skeleton_handle(ds: Dataset, alpha: float, max_depth: int, options: bns_options):
@@ -348,10 +358,34 @@ def skeleton_batch_handles(datasets, alphas, max_depths, options: bns_options):
     return [ctypes.c_void_p(outs[i]) for i in range(k)]
 
 
+def bns_orient(adj: np.ndarray, sepsets: dict) -> np.ndarray:
+    """CPDAG marks (bns_skeleton_orient) of a skeleton given on the host:
+    adj (n x n 0/1) and sepsets {(i, j): members} of every removed pair."""
+    adj = np.ascontiguousarray(adj, dtype=np.uint8)
+    n = adj.shape[0]
+    depth = np.full((n, n), -1, dtype=np.int32)
+    off = np.full((n, n), -1, dtype=np.int64)
+    pool = []
+    for (i, j), S in sorted(sepsets.items()):
+        depth[i, j] = depth[j, i] = len(S)
+        off[i, j] = off[j, i] = len(pool)
+        pool.extend(int(v) for v in S)
+    pa = np.asarray(pool if pool else [0], dtype=np.int32)
+    h = ctypes.c_void_p()
+    L = load()
+    _check(L.bns_skeleton_create(n, _ptr(adj), _ptr(depth), _ptr(off), _ptr(pa), len(pool), ctypes.byref(h)))
+    try:
+        cp = np.zeros((n, n), dtype=np.int8)
+        _check(L.bns_skeleton_orient(h, _ptr(cp)))
+        return cp
+    finally:
+        L.bns_skeleton_free(h)
+
+
 def free_skeleton(h) -> None:
     load().bns_skeleton_free(h)
 
 
-def collect(h) -> Skeleton:
+def collect(h, orient: bool = False) -> Skeleton:
     """Converts a raw result handle into a Skeleton and frees the handle."""
-    return _collect(h)
+    return _collect(h, orient)

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbns.so")
-SOURCES = ["capi.hip", "kernels.hip"]
+SOURCES = ["capi.hip", "kernels.hip", "orient.cpp"]
 ARCH = "gfx950"
 
 
@@ -38,7 +38,7 @@ def flags():
 def build(verbose: bool = False) -> str:
     objs = []
     for src in SOURCES:
-        obj = os.path.join(CSRC, src.replace(".hip", ".o"))
+        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc()] + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

@@ -17,6 +17,7 @@
 #include "../../include/bns.h"
 #include "bns_internal.h"
 #include "kernels.h"
+#include "skeleton.h"
 
 using namespace bns;
 
@@ -623,14 +624,6 @@ extern "C" bns_status bns_ci_batch_noalloc(const bns_dataset *ds, const bns_ci_t
 // ---------------------------------------------------------------------------
 // Skeleton results
 // ---------------------------------------------------------------------------
-struct bns_skeleton {
-    int32_t n = 0;
-    std::vector<uint8_t> adj;
-    std::vector<int32_t> depth;
-    std::vector<int64_t> sepoff;
-    std::vector<int32_t> pool;
-    std::vector<bns_depth_stats> stats;
-};
 
 extern "C" int32_t bns_skeleton_n_vars(const bns_skeleton *sk) { return sk ? sk->n : 0; }
 

@@ -81,10 +81,8 @@ ORIENT_MUTANTS = {
     "collider_when_in_sepset": ("if z not in sepsets[(min(x, y), max(x, y))]:",
                                 "if z in sepsets[(min(x, y), max(x, y))]:"),
     "triples_ignore_adjacency": ("                if adj[x, y]:\n                    continue\n", ""),
-    "r1_without_nonadjacency": ("if any(_directed(G, c, a) and not adj[c, b] for c in range(n) if c not in (a, b)):",
-                                "if any(_directed(G, c, a) for c in range(n) if c not in (a, b)):"),
-    "r2_reversed": ("if any(_directed(G, a, c) and _directed(G, c, b) for c in range(n) if c not in (a, b)):",
-                    "if any(_directed(G, c, a) and _directed(G, b, c) for c in range(n) if c not in (a, b)):"),
+    "r1_without_nonadjacency": ("r1 = D[:, a] & ~adj[:, b]", "r1 = D[:, a].copy()"),
+    "r2_reversed": ("if (D[a, :] & D[:, b]).any():", "if (D[:, a] & D[b, :]).any():"),
     "r3_dropped": ("            if any(not adj[c, d] for i, c in enumerate(cs) for d in cs[i + 1:]):\n"
                    "                found.add((a, b))\n", ""),
     "conflict_resolved_by_order": ("            if (b, a) not in found:\n                G[b, a] = 1",
