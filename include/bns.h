@@ -231,6 +231,17 @@ bns_status bns_ci_batch_noalloc(const bns_dataset *ds, const bns_ci_test *tests,
                                 const bns_options *opt, double *g2, int64_t *df, double *p,
                                 int32_t *flags);
 
+/* Every pairwise marginal test of ds at once: the tests of depth 0 of the
+ * skeleton search (Section IV-B: one test per pair, no conditioning set), all
+ * n(n-1)/2 tables formed together as blocks of the Gram matrix of one-hot
+ * columns (an int8 matrix-core contraction; exact integer counts).  Pair
+ * (i, j), i < j, is entry i n - i (i + 1) / 2 + j - i - 1 of each output
+ * (host arrays of n(n-1)/2 entries, any may be NULL): the statistic
+ * (opt->statistic, evaluated in FP64), df (opt->df_rule), p (FP64) and flags
+ * (BNS_CI_INDEPENDENT when p > alpha). */
+bns_status bns_ci_pairs(const bns_dataset *ds, double alpha, const bns_options *opt, double *stat,
+                        int64_t *df, double *p, int32_t *flags);
+
 /* ---------------------------------------------------------------------- */
 /* PC-stable skeleton (Algorithm 1)                                       */
 /* ---------------------------------------------------------------------- */

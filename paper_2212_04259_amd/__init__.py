@@ -28,6 +28,7 @@ from ._lib import (  # noqa: F401
     Skeleton,
     bns_ci_batch,
     bns_ci_batch_noalloc,
+    bns_ci_pairs,
     bns_dataset_create,
     bns_dataset_wrap_device,
     bns_options,

@@ -35,6 +35,7 @@ EXPORTS = [
     "bns_pc_skeleton_batch", "bns_skeleton_n_vars", "bns_skeleton_adjacency",
     "bns_skeleton_sepset", "bns_skeleton_removals", "bns_skeleton_stats", "bns_skeleton_free",
     "bns_autotune", "bns_ci_batch_noalloc", "bns_skeleton_orient", "bns_skeleton_create",
+    "bns_ci_pairs",
 ]
 NOALLOC_SCRATCH_BYTES = 16 << 20
 
@@ -127,6 +128,8 @@ def load():
     L.bns_skeleton_removals.argtypes = [vp, vp, vp, vp, i64, P(i64)]
     L.bns_skeleton_stats.restype = i32
     L.bns_skeleton_stats.argtypes = [vp, P(bns_depth_stats), i32, P(i32)]
+    L.bns_ci_pairs.restype = i32
+    L.bns_ci_pairs.argtypes = [vp, dbl, P(bns_options), vp, vp, vp, vp]
     L.bns_skeleton_create.restype = i32
     L.bns_skeleton_create.argtypes = [i32, vp, vp, vp, vp, i64, P(vp)]
     L.bns_skeleton_orient.restype = i32
@@ -222,6 +225,24 @@ def bns_ci_batch(ds: Dataset, tests, alpha: float = 0.05, options: bns_options |
     if want_tables:
         out["tables"] = [tabs[offs[t]:offs[t] + sizes[t]] for t in range(n)]
     return out
+
+
+def bns_ci_pairs(ds: Dataset, alpha: float = 0.05, options: bns_options | None = None):
+    """Every pairwise marginal test of the dataset (bns_ci_pairs).  Returns a
+    dict of numpy arrays stat, df, p, flags in the order of the pairs i < j,
+    and pairs: the (i, j) of each entry."""
+    n = ds.n_vars
+    npairs = n * (n - 1) // 2
+    stat = np.zeros(max(npairs, 1), dtype=np.float64)
+    df = np.zeros(max(npairs, 1), dtype=np.int64)
+    p = np.zeros(max(npairs, 1), dtype=np.float64)
+    flags = np.zeros(max(npairs, 1), dtype=np.int32)
+    o = options if options is not None else bns_options_default()
+    _check(load().bns_ci_pairs(ds.handle, float(alpha), ctypes.byref(o), _ptr(stat), _ptr(df), _ptr(p),
+                               _ptr(flags)))
+    ii, jj = np.triu_indices(n, 1)
+    return dict(stat=stat[:npairs], df=df[:npairs], p=p[:npairs], flags=flags[:npairs],
+                pairs=list(zip(ii.tolist(), jj.tolist())))
 
 
 def bns_ci_batch_noalloc(ds: Dataset, tests, alpha: float = 0.05, options: bns_options | None = None):

@@ -103,8 +103,6 @@ static bns_status read_options(const bns_options *in, bns_options *out) {
         return fail(BNS_E_INVALID_ARG, "options.depth0 must be a BNS_DEPTH0_* value");
     for (int i = 0; i < 3; ++i)
         if (out->reserved[i] != 0) return fail(BNS_E_INVALID_ARG, "options.reserved must be zero");
-    if (out->depth0 == BNS_DEPTH0_PAIRS)
-        return fail(BNS_E_INVALID_ARG, "options.depth0 = BNS_DEPTH0_PAIRS is not available yet");
     return BNS_OK;
 }
 
@@ -158,6 +156,8 @@ struct DevCtx {
     // skeleton search
     DevBuf setup, adj, adjbits, nbr, ipos, deg, rowcnt, rowbase, edges_tmp, edges, min_accept, rdepth, pool, ctl;
     DevBuf pstat, ecnt;  // per-problem counters of multi-dataset searches
+    DevBuf pair_part;    // partial Gram tiles of depth 0 through the pair contraction
+    DevBuf pairs_setup, pairs_out;  // bns_ci_pairs: tile plan and results
     DevBuf err_val, err_tag, err_cnt;  // verification log
     // bytes of the last search set-up uploaded into `setup` (a repeated
     // search skips the upload)
@@ -621,6 +621,158 @@ extern "C" bns_status bns_ci_batch_noalloc(const bns_dataset *ds, const bns_ci_t
     return BNS_OK;
 }
 
+// Depth 0 through the pair contraction: one-hot column maps, tiles and
+// sample chunks of every problem.
+struct PairPlan {
+    bool on = false;
+    int T = 64;
+    int64_t chunk = 0, items = 0, tiles = 0, part_bytes = 0, gram_bytes = 0;
+    std::vector<GramProb> gps;
+    std::vector<int32_t> oh_var, var_oh;
+    std::vector<uint16_t> oh_cat;
+};
+// Partial tiles held at most by the pair contraction (beyond it, depth 0
+// runs in the test kernel, or a forced pair path fails with BNS_E_NOMEM).
+static const int64_t kPairPartMax = 1ll << 30;
+
+static bns_status plan_pairs(const DevCtx &dc, const bns_dataset *const *ds, int32_t P, PairPlan &pp) {
+    pp = PairPlan();
+    int64_t rmax = 0, m_max = 1;
+    for (int32_t k = 0; k < P; ++k) {
+        int64_t R = 0;
+        for (uint8_t c : ds[k]->cards) R += c;
+        rmax = std::max(rmax, R);
+        m_max = std::max(m_max, ds[k]->m);
+    }
+    pp.T = rmax >= 512 ? 128 : 64;
+    const int64_t T = pp.T;
+    int64_t tiles = 0;
+    std::vector<int64_t> tiles_k((size_t)P);
+    for (int32_t k = 0; k < P; ++k) {
+        int64_t R = 0;
+        for (uint8_t c : ds[k]->cards) R += c;
+        const int64_t nb = (R + T - 1) / T;
+        tiles_k[k] = nb * (nb + 1) / 2;
+        tiles += tiles_k[k];
+    }
+    // about two work items per workgroup slot of the device: split the
+    // samples into chunks when the tiles alone are fewer
+    const int64_t want = 2ll * dc.num_cu * gram_max_wg_per_cu(pp.T);
+    int64_t chunk = (m_max + 63) / 64 * 64;
+    if (tiles < want) chunk = std::max<int64_t>(2048, ((m_max * tiles + want - 1) / want + 63) / 64 * 64);
+    pp.chunk = std::min(chunk, (m_max + 63) / 64 * 64);
+    pp.gps.resize((size_t)P);
+    pp.var_oh.clear();
+    for (int32_t k = 0; k < P; ++k) {
+        const bns_dataset *d = ds[k];
+        GramProb &g = pp.gps[k];
+        g.data = d->d_data;
+        g.ld = d->ld;
+        g.m = d->m;
+        g.oh_base = (int32_t)pp.oh_var.size();
+        int32_t R = 0;
+        for (int32_t v = 0; v < d->n; ++v) {
+            pp.var_oh.push_back(R);
+            const uint16_t wide = d->cards[v] > 8 ? 0x100 : 0;
+            for (int x = 0; x < d->cards[v]; ++x) {
+                pp.oh_var.push_back(v);
+                pp.oh_cat.push_back((uint16_t)(x | wide));
+            }
+            R += d->cards[v];
+        }
+        const int64_t Rp = (R + T - 1) / T * T;
+        for (int64_t c = R; c < Rp; ++c) {
+            pp.oh_var.push_back(-1);
+            pp.oh_cat.push_back(0);
+        }
+        g.R = (int32_t)Rp;
+        g.nb = (int32_t)(Rp / T);
+        g.nchunks = (int32_t)((d->m + pp.chunk - 1) / pp.chunk);
+        g.item_base = pp.items;
+        g.tile_base = pp.tiles;
+        pp.items += tiles_k[k] * g.nchunks;
+        pp.tiles += tiles_k[k];
+    }
+    pp.part_bytes = pp.items * T * T * 4;
+    pp.gram_bytes = pp.items > pp.tiles ? pp.tiles * T * T * 4 : 0;  // summed tiles (when chunks were split)
+    if (pp.part_bytes + pp.gram_bytes > kPairPartMax || (int64_t)pp.oh_var.size() > INT32_MAX) {
+        const double mib = (double)(pp.part_bytes + pp.gram_bytes) / 1048576.0;
+        pp = PairPlan();
+        return fail(BNS_E_NOMEM, "depth 0 through the pair contraction needs %.0f MiB of partial tiles (limit %lld MiB)",
+                    mib, (long long)(kPairPartMax >> 20));
+    }
+    pp.on = true;
+    return BNS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// bns_ci_pairs: every pairwise marginal test of a dataset through the pair
+// contraction.
+// ---------------------------------------------------------------------------
+extern "C" bns_status bns_ci_pairs(const bns_dataset *ds, double alpha, const bns_options *opt, double *stat,
+                                   int64_t *df, double *p, int32_t *flags) {
+    if (!ds) return fail(BNS_E_INVALID_ARG, "dataset is NULL");
+    if (!(alpha > 0.0 && alpha < 1.0)) return fail(BNS_E_INVALID_ARG, "alpha must be in (0, 1)");
+    bns_options o;
+    bns_status st = read_options(opt, &o);
+    if (st != BNS_OK) return st;
+    DevCtx *dc = nullptr;
+    st = get_ctx(ds->device, &dc);
+    if (st != BNS_OK) return st;
+    DeviceGuard dg(ds->device);
+    if (!dg.ok) return fail(BNS_E_DEVICE, "cannot select device %d", ds->device);
+    std::lock_guard<std::mutex> lk(dc->mu);
+    hipStream_t s = o.stream ? (hipStream_t)o.stream : dc->stream;
+    PairPlan pp;
+    st = plan_pairs(*dc, &ds, 1, pp);
+    if (st != BNS_OK) return st;
+    const int64_t n = ds->n, npairs = n * (n - 1) / 2;
+    auto al8 = [](size_t x) { return (x + 7) & ~(size_t)7; };
+    const size_t o_ohvar = al8(sizeof(GramProb));
+    const size_t o_ohcat = al8(o_ohvar + sizeof(int32_t) * pp.oh_var.size());
+    const size_t o_varoh = al8(o_ohcat + sizeof(uint16_t) * pp.oh_cat.size());
+    const size_t setup_bytes = al8(o_varoh + sizeof(int32_t) * pp.var_oh.size());
+    const size_t out_bytes = (size_t)npairs * (8 + 8 + 8 + 4) + 32;
+    st = check_workspace(o, (double)(setup_bytes + out_bytes + pp.part_bytes + pp.gram_bytes), "bns_ci_pairs");
+    if (st != BNS_OK) return st;
+    std::vector<char> h(setup_bytes, 0);
+    std::memcpy(h.data(), pp.gps.data(), sizeof(GramProb));
+    std::memcpy(h.data() + o_ohvar, pp.oh_var.data(), sizeof(int32_t) * pp.oh_var.size());
+    std::memcpy(h.data() + o_ohcat, pp.oh_cat.data(), sizeof(uint16_t) * pp.oh_cat.size());
+    std::memcpy(h.data() + o_varoh, pp.var_oh.data(), sizeof(int32_t) * pp.var_oh.size());
+    HIP_TRY(dc->pairs_setup.ensure(setup_bytes));
+    HIP_TRY(dc->pair_part.ensure((size_t)(pp.part_bytes + pp.gram_bytes)));
+    HIP_TRY(dc->pairs_out.ensure(out_bytes));
+    HIP_TRY(hipMemcpyAsync(dc->pairs_setup.p, h.data(), setup_bytes, hipMemcpyHostToDevice, s));
+    char *sb = dc->pairs_setup.as<char>();
+    PairArgs pa;
+    std::memset(&pa, 0, sizeof(pa));
+    pa.gp = (const GramProb *)sb;
+    pa.oh_var = (const int32_t *)(sb + o_ohvar);
+    pa.oh_cat = (const uint16_t *)(sb + o_ohcat);
+    pa.var_oh = (const int32_t *)(sb + o_varoh);
+    pa.part = dc->pair_part.as<int32_t>();
+    pa.gram = pp.gram_bytes ? pa.part + pp.part_bytes / 4 : pa.part;
+    pa.items = pp.items;
+    pa.tiles = pp.tiles;
+    pa.chunk = pp.chunk;
+    pa.T = pp.T;
+    pa.n_gp = 1;
+    pa.gram_grid = (int)std::min<int64_t>(pp.items, (int64_t)dc->num_cu * gram_max_wg_per_cu(pp.T));
+    char *ob = dc->pairs_out.as<char>();
+    double *d_stat = (double *)ob;
+    double *d_p = d_stat + npairs;
+    int64_t *d_df = (int64_t *)(d_p + npairs);
+    int32_t *d_fl = (int32_t *)(d_df + npairs);
+    HIP_TRY(launch_ci_pairs(pa, ds->d_cards, ds->n, alpha, o.statistic, o.df_rule, d_stat, d_df, d_p, d_fl, s));
+    if (stat) HIP_TRY(hipMemcpyAsync(stat, d_stat, sizeof(double) * (size_t)npairs, hipMemcpyDeviceToHost, s));
+    if (p) HIP_TRY(hipMemcpyAsync(p, d_p, sizeof(double) * (size_t)npairs, hipMemcpyDeviceToHost, s));
+    if (df) HIP_TRY(hipMemcpyAsync(df, d_df, sizeof(int64_t) * (size_t)npairs, hipMemcpyDeviceToHost, s));
+    if (flags) HIP_TRY(hipMemcpyAsync(flags, d_fl, sizeof(int32_t) * (size_t)npairs, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return BNS_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Skeleton results
 // ---------------------------------------------------------------------------
@@ -734,7 +886,7 @@ static bns_status depth_graph(DevCtx &dc, const DepthArgs &a, int grid, int K, b
     hipError_t e = init ? launch_init_search(a, s) : hipSuccess;
     for (int i = 0; i < K && e == hipSuccess; ++i) {
         e = launch_depth_prepare(a, s);
-        if (e == hipSuccess) e = launch_depth_tests(a, grid, s);
+        if (e == hipSuccess) e = (init && i == 0 && a.pairs.part) ? launch_depth0_pairs(a, s) : launch_depth_tests(a, grid, s);
         if (e == hipSuccess) e = launch_depth_apply(a, s);
     }
     if (e == hipSuccess) e = launch_publish(a, s);
@@ -811,9 +963,20 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     const size_t o_binom = al8(o_probs + sizeof(ProbDev) * (size_t)P);
     const size_t o_v2p = al8(o_binom + sizeof(uint64_t) * B.size());
     const size_t o_cards = al8(o_v2p + sizeof(int32_t) * (size_t)G);
-    const size_t setup_bytes = al8(o_cards + (size_t)G);
     const bool per_prob = P > 1;
     const bool verify = o.report_errors != 0 && o.precision == BNS_PREC_FP32_RECHECK;
+    // Depth 0 through the pair contraction (verification mode keeps the test
+    // kernel, whose FP32 statistic it compares with FP64).
+    PairPlan pp;
+    if (!verify && o.depth0 == BNS_DEPTH0_PAIRS) {
+        st = plan_pairs(dc, ds, P, pp);
+        if (st != BNS_OK) return st;
+    }
+    const size_t o_gp = al8(o_cards + (size_t)G);
+    const size_t o_ohvar = al8(o_gp + sizeof(GramProb) * pp.gps.size());
+    const size_t o_ohcat = al8(o_ohvar + sizeof(int32_t) * pp.oh_var.size());
+    const size_t o_varoh = al8(o_ohcat + sizeof(uint16_t) * pp.oh_cat.size());
+    const size_t setup_bytes = al8(o_varoh + sizeof(int32_t) * pp.var_oh.size());
     const int64_t err_cap = verify ? kErrLogEntries : 0;
     const size_t rbytes = ((size_t)adj_total + 7) & ~(size_t)7;  // removal depths, padded for 8-byte copies
     {
@@ -824,7 +987,7 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
                             16.0 * G + (2.0 * sizeof(EdgeRec) + 8.0) * (double)pairs_total + sizeof(Ctl) +
                             4.0 * (double)kSplitWords + 4.0 * (double)kSplitTickets +
                             4.0 * 1024 + (per_prob ? sizeof(PStatDev) * (double)P * kMaxDepths + 8.0 * pairs_total : 0.0) +
-                            8.0 * (double)err_cap;
+                            8.0 * (double)err_cap + (double)(pp.part_bytes + pp.gram_bytes);
         st = check_workspace(o, need, "the skeleton search");
         if (st != BNS_OK) return st;
     }
@@ -836,6 +999,12 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
         std::memcpy(h + o_binom, B.data(), sizeof(uint64_t) * B.size());
         std::memcpy(h + o_v2p, var2prob.data(), sizeof(int32_t) * (size_t)G);
         std::memcpy(h + o_cards, gcards.data(), (size_t)G);
+        if (pp.on) {
+            std::memcpy(h + o_gp, pp.gps.data(), sizeof(GramProb) * pp.gps.size());
+            std::memcpy(h + o_ohvar, pp.oh_var.data(), sizeof(int32_t) * pp.oh_var.size());
+            std::memcpy(h + o_ohcat, pp.oh_cat.data(), sizeof(uint16_t) * pp.oh_cat.size());
+            std::memcpy(h + o_varoh, pp.var_oh.data(), sizeof(int32_t) * pp.var_oh.size());
+        }
     }
     if (!(dc.setup_last_dev == dc.setup.p && dc.setup_last.size() == setup_bytes &&
           std::memcmp(dc.setup_last.data(), dc.hpin, setup_bytes) == 0)) {
@@ -865,6 +1034,7 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     }
     HIP_TRY(dc.pstat.ensure(per_prob ? sizeof(PStatDev) * (size_t)P * kMaxDepths : 256));
     HIP_TRY(dc.ecnt.ensure(per_prob ? sizeof(uint32_t) * 2 * (size_t)pairs_total : 256));
+    if (pp.on) HIP_TRY(dc.pair_part.ensure((size_t)(pp.part_bytes + pp.gram_bytes)));
     if (!dc.split_tab.p || dc.split_dirty) {
         HIP_TRY(dc.split_tab.ensure(sizeof(uint32_t) * (size_t)kSplitWords));
         HIP_TRY(dc.split_cnt.ensure(sizeof(uint32_t) * (size_t)kSplitTickets));
@@ -923,6 +1093,21 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     // XCD); else one at a time.
     const bool runs = o.ticket_runs == 2 || (o.ticket_runs == 0 && col_bytes > kGrabRunBytes);
     a.grab_block_log2 = runs ? kGrabRunLog2 : 0;
+    if (pp.on) {
+        char *sb = dc.setup.as<char>();
+        a.pairs.gp = (const GramProb *)(sb + o_gp);
+        a.pairs.oh_var = (const int32_t *)(sb + o_ohvar);
+        a.pairs.oh_cat = (const uint16_t *)(sb + o_ohcat);
+        a.pairs.var_oh = (const int32_t *)(sb + o_varoh);
+        a.pairs.part = dc.pair_part.as<int32_t>();
+        a.pairs.gram = pp.gram_bytes ? a.pairs.part + pp.part_bytes / 4 : a.pairs.part;
+        a.pairs.items = pp.items;
+        a.pairs.tiles = pp.tiles;
+        a.pairs.chunk = pp.chunk;
+        a.pairs.T = pp.T;
+        a.pairs.n_gp = P;
+        a.pairs.gram_grid = (int)std::min<int64_t>(pp.items, (int64_t)dc.num_cu * gram_max_wg_per_cu(pp.T));
+    }
 
     const int lds_bytes = tile.lds_words * 4;
     int wg = o.wg_per_cu ? o.wg_per_cu : depth_tests_max_wg_per_cu(lds_bytes);
@@ -1010,8 +1195,15 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
             if (d == 0) HIP_TRY(launch_init_search(a, s));
             for (int i = 0; i < K; ++i) {
                 HIP_TRY(launch_depth_prepare(a, s));
-                if (o.timing) HIP_TRY(launch_depth_tests(a, grid, s, evg.v[2 * i], evg.v[2 * i + 1]));
-                else HIP_TRY(launch_depth_tests(a, grid, s));
+                if (d == 0 && i == 0 && a.pairs.part) {
+                    if (o.timing) HIP_TRY(hipEventRecord(evg.v[0], s));
+                    HIP_TRY(launch_depth0_pairs(a, s));
+                    if (o.timing) HIP_TRY(hipEventRecord(evg.v[1], s));
+                } else if (o.timing) {
+                    HIP_TRY(launch_depth_tests(a, grid, s, evg.v[2 * i], evg.v[2 * i + 1]));
+                } else {
+                    HIP_TRY(launch_depth_tests(a, grid, s));
+                }
                 HIP_TRY(launch_depth_apply(a, s));
             }
             HIP_TRY(launch_publish(a, s));

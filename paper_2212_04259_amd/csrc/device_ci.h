@@ -243,6 +243,59 @@ static __device__ __noinline__ Tail chi2_tail_wave(int64_t df, double g2) {
     return r;
 }
 
+// The same upper tail evaluated by one lane alone (each lane its own df and
+// statistic; no lane exchange): for df <= 128 the closed forms above with the
+// terms formed one after another; beyond, the power series of the lower
+// function (x below a + 1 + 3 sqrt a) or Legendre's continued fraction by the
+// modified Lentz method (Numerical Recipes, 6.2), both run to convergence.
+[[maybe_unused]] static __device__ double chi2_tail_lane(int64_t df, double g2) {
+    if (df <= 0) return 1.0;
+    const double x = 0.5 * g2;
+    if (!(x > 0.0)) return 1.0;
+    const double pi = 3.141592653589793;
+    if (df <= 128) {
+        if (x > 700.0) return 0.0;  // e^-x underflows; the tail is below 1e-200
+        const int n = (int)(df >> 1);
+        const bool odd = (df & 1) != 0;
+        const double h = odd ? 0.5 : 0.0;
+        double term = odd ? 2.0 * sqrt(x / pi) : 1.0;  // x^(k+h) / Gamma(k+h+1) at k = 0
+        double S = 0.0;
+        for (int k = 0; k < n; ++k) {
+            S += term;
+            term *= x / ((double)(k + 1) + h);
+        }
+        const double p = (odd ? erfc(sqrt(x)) : 0.0) + exp(-x) * S;
+        return p > 1.0 ? 1.0 : p;
+    }
+    const double a = 0.5 * (double)df;
+    const double lx = log(x);
+    if (x < a + 1.0 + 3.0 * sqrt(a)) {
+        double term = 1.0, sum = 1.0;
+        for (int k = 1; k < 1000000; ++k) {
+            term *= x / (a + (double)k);
+            sum += term;
+            if (term < sum * 1e-17) break;
+        }
+        const double lower = exp(a * lx - x - lgamma(a + 1.0)) * sum;
+        return lower >= 1.0 ? 0.0 : 1.0 - lower;
+    }
+    const double fpmin = 1e-300;
+    double bk = x + 1.0 - a, C = 1.0 / fpmin, D = 1.0 / bk, H = D;
+    for (int k = 1; k < 1000000; ++k) {
+        const double ak = (double)k * (a - (double)k);
+        bk += 2.0;
+        D = bk + ak * D;
+        D = (fabs(D) < fpmin) ? fpmin : D;
+        C = bk + ak / C;
+        C = (fabs(C) < fpmin) ? fpmin : C;
+        D = 1.0 / D;
+        const double step = C * D;
+        H *= step;
+        if (fabs(step - 1.0) <= 2.220446049250313e-16) break;
+    }
+    return exp(a * lx - x - lgamma(a)) * H;
+}
+
 // ---------------------------------------------------------------------------
 // One cell's share of G^2 / 2 in a form whose terms are all non-negative.
 //

@@ -8,6 +8,41 @@
 
 namespace bns {
 
+// Depth 0 as one contraction (Section IV-B: depth 0 tests every pair with no
+// conditioning set).  With one-hot columns A[s][(v, x)] = [X_v(s) = x], every
+// pairwise table is a block of the Gram matrix A^T A: N_ij[x][y] =
+// (A^T A)[(i, x)][(j, y)], and the diagonal holds each category's count.
+// The Gram matrix of each problem is computed in T x T tiles (upper triangle
+// of tile blocks) over chunks of samples; each (tile, chunk) work item writes
+// its partial tile, and the pair kernel sums a pair's block over the chunks.
+struct GramProb {
+    const uint8_t *data;   // column v at data + v * ld
+    int64_t ld;
+    int64_t m;
+    int32_t R;             // one-hot columns, padded to a multiple of T
+    int32_t nb;            // tile blocks per side (R / T)
+    int32_t oh_base;       // first entry of the problem in oh_var / oh_cat
+    int32_t nchunks;       // sample chunks of the problem
+    int64_t item_base;     // first work item of the problem
+    int64_t tile_base;     // first tile of the problem in the summed tiles
+};
+
+struct PairArgs {
+    const GramProb *gp;    // per problem
+    const int32_t *oh_var; // one-hot column -> variable of the problem (-1: padding column)
+    const uint16_t *oh_cat; // category of the column (low byte); bit 8: the variable has more than 8 categories
+    const int32_t *var_oh; // global variable -> its first one-hot column within its problem
+    int32_t *part;         // partial tiles, T * T int32 per work item (null: depth 0 uses the test kernel)
+    int32_t *gram;         // tiles summed over the chunks, T * T int32 per tile (= part when no problem has two chunks)
+    int64_t items;         // work items over all problems
+    int64_t tiles;         // tiles over all problems
+    int64_t chunk;         // samples per chunk (a multiple of 64)
+    int32_t T;             // tile side: 64 or 128
+    int32_t n_gp;
+    int32_t gram_grid;     // workgroups of the tile kernel
+    int32_t pad;
+};
+
 // Arguments of the per-depth pipeline of a skeleton search (all device pointers).
 struct DepthArgs {
     const ProbDev *probs;
@@ -76,6 +111,7 @@ struct DepthArgs {
     unsigned long long *pub_seq;  // device: launches published so far
     unsigned int *pub_cnt;        // device: workgroups of the current publish done (0 between)
     unsigned long long *h_flag;   // pinned host
+    PairArgs pairs;               // depth 0 as one contraction (pairs.part non-null)
 };
 
 // Small searches keep the adjacency as bit rows in LDS and prepare each depth
@@ -91,6 +127,14 @@ hipError_t launch_depth_tests(const DepthArgs &a, int grid, hipStream_t s,
 hipError_t launch_depth_apply(const DepthArgs &a, hipStream_t s);     // removals + finalize
 hipError_t launch_init_search(const DepthArgs &a, hipStream_t s);     // complete graph, reset
 hipError_t launch_publish(const DepthArgs &a, hipStream_t s);         // results into pinned host memory
+// Depth 0 through the pair contraction: Gram tiles, then one decision per pair
+// (in place of the depth's test kernel).
+hipError_t launch_depth0_pairs(const DepthArgs &a, hipStream_t s);
+// Every pairwise test of one dataset (pair index i n - i (i + 1) / 2 + j - i - 1).
+hipError_t launch_ci_pairs(const PairArgs &p, const uint8_t *cards, int32_t n, double alpha, int stat,
+                           int df_rule, double *stat_out, int64_t *df_out, double *p_out, int32_t *flags_out,
+                           hipStream_t s);
+int gram_max_wg_per_cu(int T);
 int depth_tests_max_wg_per_cu(int lds_bytes);
 int depth_tests_fit_lds(int lds_per_cu);  // default dynamic LDS at full occupancy
 hipError_t allow_dynamic_lds(int bytes);  // raises the per-kernel dynamic LDS limit
