@@ -146,10 +146,13 @@ enum {
 
 /* Depth-0 path of the batched form. */
 enum {
-    BNS_DEPTH0_AUTO = 0,    /* the library chooses */
+    BNS_DEPTH0_AUTO = 0,    /* PAIRS when the depth's pair-samples (pairs times samples, summed
+                               over the problems) reach 5e8 and the partial tiles fit, else TESTS */
     BNS_DEPTH0_TESTS = 1,   /* the depth's tests run in the per-depth test kernel */
     BNS_DEPTH0_PAIRS = 2    /* all pairwise tables at once as one contraction of one-hot
-                               columns (Section IV-B: depth 0 tests every pair) */
+                               columns (Section IV-B: depth 0 tests every pair); the
+                               statistic is evaluated in FP64.  Verification mode
+                               (report_errors) keeps depth 0 in the test kernel */
 };
 
 /* Fills *opt with the defaults.  opt must not be NULL. */

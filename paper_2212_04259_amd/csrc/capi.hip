@@ -634,6 +634,11 @@ struct PairPlan {
 // Partial tiles held at most by the pair contraction (beyond it, depth 0
 // runs in the test kernel, or a forced pair path fails with BNS_E_NOMEM).
 static const int64_t kPairPartMax = 1ll << 30;
+// Depth 0 through the contraction in automatic mode from this many
+// pair-samples (pairs times samples summed over the problems) on: measured on
+// MI355X, 8.9e7 (60 variables, 50,000 samples) is faster in the test kernel,
+// 2.4e9 (220 variables, 100,000 samples) and more through the contraction.
+static const double kPairsAutoWork = 5e8;
 
 static bns_status plan_pairs(const DevCtx &dc, const bns_dataset *const *ds, int32_t P, PairPlan &pp) {
     pp = PairPlan();
@@ -971,6 +976,12 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     if (!verify && o.depth0 == BNS_DEPTH0_PAIRS) {
         st = plan_pairs(dc, ds, P, pp);
         if (st != BNS_OK) return st;
+    } else if (!verify && o.depth0 == BNS_DEPTH0_AUTO) {
+        // the contraction's fixed cost (three launches, latency-bound
+        // steps) pays once the depth's counting work is large
+        double work = 0.0;
+        for (int32_t k = 0; k < P; ++k) work += 0.5 * (double)ds[k]->n * (ds[k]->n - 1) * (double)ds[k]->m;
+        if (work >= kPairsAutoWork && plan_pairs(dc, ds, P, pp) != BNS_OK) pp = PairPlan();
     }
     const size_t o_gp = al8(o_cards + (size_t)G);
     const size_t o_ohvar = al8(o_gp + sizeof(GramProb) * pp.gps.size());
