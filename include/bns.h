@@ -65,7 +65,11 @@ typedef enum bns_status {
 /* Execution form of the skeleton search. */
 enum {
     BNS_FORM_BATCHED = 0, /* device-resident per-depth work queue, one persistent launch per depth */
-    BNS_FORM_PLAIN = 1    /* host walks the tests in order; one sample-parallel launch per test */
+    BNS_FORM_PLAIN = 1,   /* host walks the tests in order; one sample-parallel launch per test */
+    BNS_FORM_EDGE = 2     /* one persistent launch per depth in which each group of lanes (a wave,
+                             or a workgroup with test_group 2) takes one edge at a time and runs
+                             its tests in order until the first accepting one (the edge-level
+                             parallelism of Section IV-A: no speculative test) */
 };
 
 /* Arithmetic of the G^2 log-sum (counts are always exact integers and the
@@ -124,7 +128,15 @@ typedef struct bns_options {
     int32_t df_rule;       /* BNS_DF_*: the degrees of freedom (default BNS_DF_DECLARED) */
     int32_t depth0;        /* batched form, depth 0 (one marginal test per pair):
                               BNS_DEPTH0_* (default automatic) */
-    int32_t reserved[3];   /* must be zero */
+    int32_t round_tests;   /* batched form: ranks of an edge per level of the depth's work queue
+                              (the counterpart of the group size gs of Section IV-B).  The
+                              queue holds level after level, each giving every edge that still
+                              has tests its next ranks: 0 = levels of 1, 1, 2, 4, 8, ... ranks
+                              (default); g in [1, 65536] = levels of g ranks (the last of 64
+                              levels takes the rest).  A test whose edge has accepted at a
+                              lower rank is skipped when it is taken; those run before the
+                              accept was seen count as executed (speculative) tests */
+    int32_t reserved[2];   /* must be zero */
     void *stream;          /* hipStream_t; NULL = default stream */
 } bns_options;
 

@@ -15,6 +15,7 @@ from ._lib import (  # noqa: F401
     BNS_DF_ADJUSTED,
     BNS_DF_DECLARED,
     BNS_FORM_BATCHED,
+    BNS_FORM_EDGE,
     BNS_FORM_PLAIN,
     BNS_PREC_FP32_RECHECK,
     BNS_PREC_FP64,

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbns.so")
 
 BNS_OK = 0
-BNS_FORM_BATCHED, BNS_FORM_PLAIN = 0, 1
+BNS_FORM_BATCHED, BNS_FORM_PLAIN, BNS_FORM_EDGE = 0, 1, 2
 BNS_PREC_FP32_RECHECK, BNS_PREC_FP64 = 0, 1
 BNS_CI_INDEPENDENT, BNS_CI_RECHECKED = 1, 2
 BNS_STAT_G2, BNS_STAT_X2 = 0, 1
@@ -57,7 +57,8 @@ class bns_options(ctypes.Structure):
                 ("block_depths", ctypes.c_uint32), ("report_errors", ctypes.c_int32),
                 ("workspace_mb", ctypes.c_int32), ("statistic", ctypes.c_int32),
                 ("df_rule", ctypes.c_int32), ("depth0", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3), ("stream", ctypes.c_void_p)]
+                ("round_tests", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
+                ("stream", ctypes.c_void_p)]
 
 
 class bns_ci_test(ctypes.Structure):

@@ -87,6 +87,7 @@ struct Ctl {
     unsigned long long pool_used;      // sepset members written so far
     unsigned int apply_done;           // blocks of the removal kernel that finished
     int32_t maxdeg;                    // largest frozen adjacency set at this depth
+    unsigned long long maxn;           // most tests of one edge at this depth (fixed-width levels)
     int32_t mode;                      // test kernel: 0 one test per wave, 1 per workgroup
     int32_t batch;                     // work units taken per grab
     int32_t chunks;                    // sample chunks per test (1: tests are not split)

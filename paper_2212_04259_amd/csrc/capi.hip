@@ -67,8 +67,8 @@ static bns_status read_options(const bns_options *in, bns_options *out) {
     bns_options_default(out);
     if (!in) return BNS_OK;
     *out = *in;
-    if (out->form != BNS_FORM_BATCHED && out->form != BNS_FORM_PLAIN)
-        return fail(BNS_E_INVALID_ARG, "options.form must be BNS_FORM_BATCHED or BNS_FORM_PLAIN");
+    if (out->form != BNS_FORM_BATCHED && out->form != BNS_FORM_PLAIN && out->form != BNS_FORM_EDGE)
+        return fail(BNS_E_INVALID_ARG, "options.form must be a BNS_FORM_* value");
     if (out->precision != BNS_PREC_FP32_RECHECK && out->precision != BNS_PREC_FP64)
         return fail(BNS_E_INVALID_ARG, "options.precision must be a BNS_PREC_* value");
     if (!(out->recheck_band >= 0.0) || out->recheck_band > 1.0)
@@ -101,7 +101,9 @@ static bns_status read_options(const bns_options *in, bns_options *out) {
         return fail(BNS_E_INVALID_ARG, "options.df_rule must be a BNS_DF_* value");
     if (out->depth0 < BNS_DEPTH0_AUTO || out->depth0 > BNS_DEPTH0_PAIRS)
         return fail(BNS_E_INVALID_ARG, "options.depth0 must be a BNS_DEPTH0_* value");
-    for (int i = 0; i < 3; ++i)
+    if (out->round_tests < 0 || out->round_tests > 65536)
+        return fail(BNS_E_INVALID_ARG, "options.round_tests must be in [0, 65536]");
+    for (int i = 0; i < 2; ++i)
         if (out->reserved[i] != 0) return fail(BNS_E_INVALID_ARG, "options.reserved must be zero");
     return BNS_OK;
 }
@@ -1098,6 +1100,8 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     a.mode_policy = o.test_group;
     a.wave_depths = o.wave_depths;
     a.block_depths = o.block_depths;
+    a.round_width = o.round_tests;
+    a.edge_form = o.form == BNS_FORM_EDGE ? 1 : 0;
     a.grab_fixed = o.tickets_per_grab;
     // Columns beyond a quarter of the last-level cache: deal the tickets to
     // the grab counters in runs of 64 (edges that share a column run on one

@@ -100,7 +100,10 @@ struct DepthArgs {
     int32_t grab_block_log2;  // test kernel: units dealt to a grab counter in runs of 2^this (0 or kGrabRunLog2)
     uint32_t wave_depths;     // depths d < 32 with bit d set: one test per wave (overrides mode_policy)
     uint32_t block_depths;    // same, one test per workgroup
-    int32_t pad2;
+    int32_t round_width;      // ticket levels: 0 doubling (level L: ranks [2^L - 1, 2^(L+1) - 1)); g > 0
+                              // rounds of g ranks (level L < 63: [L g, (L + 1) g); level 63: the rest)
+    int32_t edge_form;        // 1: one group per edge runs its tests in order to the first accept
+    int32_t pad2[2];
     // Results of a launch, written into pinned host memory by its last kernel.
     Ctl *h_ctl;               // copy of the control block
     char *h_res;              // null, or removal depths (res_rbytes) then the first removal records

@@ -71,6 +71,16 @@ __global__ void k_plain_count(const uint8_t *data, int64_t ld, int64_t m, const 
                               const PlainTest pt, int64_t spb, uint32_t *partials, int64_t T,
                               int lds_words);
 
+// Ticket levels of an edge with n tests: with doubling levels (g = 0) level L
+// holds ranks [2^L - 1, 2^(L+1) - 1), so 64 - clz(n) levels; with rounds of g
+// ranks, ceil(n / g) levels, at most 64 (the last one takes the rest).
+BNS_INLINE int edge_levels(uint64_t n, int g) {
+    if (n == 0) return 0;
+    if (g <= 0) return 64 - __clzll(n);
+    const uint64_t k = (n + (uint64_t)g - 1) / (uint64_t)g;
+    return k > 64 ? 64 : (int)k;
+}
+
 // ---------------------------------------------------------------------------
 // Search initialisation: complete graph, no removals, control block reset.
 // ---------------------------------------------------------------------------
@@ -201,6 +211,7 @@ __global__ __launch_bounds__(kWG) void k_scan_rows(DepthArgs A) {
         int m2 = 0;
         for (int i = 0; i < kWG; ++i) m2 = max(m2, mdeg[i]);
         c->maxdeg = m2;
+        c->maxn = 0;
         c->total_tickets = 0;
         if (c->depth >= kMaxDepths) c->error = kDevDepthTooLarge;
     }
@@ -263,8 +274,9 @@ BNS_INLINE void edges_row(const DepthArgs &A, Ctl *c, int g, unsigned int *hist)
             e.pB = du - 1;
             e.posi = 0;
             if (nB > 0) e.posi = A.ipos[P.adj_off + (int64_t)u * n + v];  // v in a(u)
-            e.levels = ntot ? 64 - __clzll(ntot) : 0;
+            e.levels = edge_levels(ntot, A.round_width);
             atomicAdd(&hist[e.levels], 1u);
+            if (A.round_width > 0 && ntot) atomicMax(&c->maxn, (unsigned long long)ntot);
             A.edges_tmp[base + hi + __popcll(mhi & lt)] = e;
             tk_sum += ntot;
         }
@@ -309,7 +321,8 @@ constexpr int kWaveModeDeepDepth = 3;
 constexpr int kWaveModeSmallDepth = 2;
 
 BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist, int d, int maxdeg,
-                            unsigned int *cursor_lds = nullptr, int *done_lds = nullptr) {
+                            unsigned long long maxn, unsigned int *cursor_lds = nullptr,
+                            int *done_lds = nullptr) {
     const int lane = threadIdx.x & 63;
     // binomial slice of the depth for the test kernel, work-unit counters
     const int brows = maxdeg + 1;
@@ -343,13 +356,19 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
             cursor_lds[kMaxLevels] = hist[kMaxLevels + 1];
         }
     }
-    // level L (= lane): cnt = edges with levels > L, tickets cnt * 2^L
+    // level L (= lane): cnt = edges with levels > L, tickets cnt * width(L),
+    // width 2^L (doubling) or g (the last of 64 rounds: up to the most tests
+    // of an edge)
     const unsigned long long cnt = start;
+    const int g = A.round_width;
+    unsigned long long width = 1ull << (lane < 62 ? lane : 62);
+    if (g > 0) width = lane < 63 ? (unsigned long long)g
+                                 : (maxn > 63ull * g ? maxn - 63ull * g : (unsigned long long)g);
     int bad = 0;
     unsigned long long tk = 0;
     if (cnt) {
-        if (lane >= 60 || cnt > ((1ull << 61) >> lane)) bad = 1;
-        else tk = cnt << lane;
+        if ((g <= 0 && lane >= 60) || cnt > (1ull << 61) / width) bad = 1;
+        else tk = cnt * width;
     }
     unsigned long long pre = tk;  // inclusive prefix over lanes <= lane
 #pragma unroll
@@ -433,7 +452,7 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
 __global__ void k_levels(DepthArgs A) {
     Ctl *c = A.ctl;
     if (c->done) return;
-    levels_wave(A, c, c->hist, c->depth, c->maxdeg);
+    levels_wave(A, c, c->hist, c->depth, c->maxdeg, c->maxn);
 }
 
 // Scatter into level order and reset the per-edge first-accept ranks.  The
@@ -512,6 +531,7 @@ struct SmallSh {
     int h_done, h_depth, h_maxdeg, h_bstride, h_brows;
     unsigned long long h_edges;
     unsigned long long pool_ctr;  // removal-record words used (the removal kernel's own counter)
+    unsigned long long maxn;      // most tests of one edge at the depth being prepared
 };
 
 // Tests of edge (v, u) at depth d from the frozen degrees (0 when the depth
@@ -612,6 +632,7 @@ BNS_INLINE void prepare_block(const DepthArgs &A, Ctl *c, int d, SmallSh &sh) {
     const int sbits = 64 >> lgL;         // bits per slice
     const uint64_t smask = (sbits == 64) ? ~0ull : ((1ull << sbits) - 1ull);
     for (int i = threadIdx.x; i < kMaxLevels + 2; i += kSmallThreads) sh.hist[i] = 0;
+    if (threadIdx.x == 0) sh.maxn = 0;
     // degrees and higher-neighbour counts, one thread per variable
     for (int g = threadIdx.x; g < G; g += kSmallThreads) {
         const ProbDev &P = small_prob(A, sh, small_prob_index(A, sh, g));
@@ -690,11 +711,12 @@ BNS_INLINE void prepare_block(const DepthArgs &A, Ctl *c, int d, SmallSh &sh) {
             uint64_t nA, nB;
             small_counts(c, sh, depth_ok, d, dv, sh.deg[P.var_off + u], nA, nB);
             const uint64_t nt = nA + nB;
-            atomicAdd(&sh.hist[nt ? 64 - __clzll(nt) : 0], 1u);
+            atomicAdd(&sh.hist[edge_levels(nt, A.round_width)], 1u);
+            if (A.round_width > 0 && nt) atomicMax(&sh.maxn, (unsigned long long)nt);
         }
     }
     __syncthreads();
-    if (w == 0) levels_wave(A, c, sh.hist, d, maxdeg, sh.cursor, &sh.done);
+    if (w == 0) levels_wave(A, c, sh.hist, d, maxdeg, sh.maxn, sh.cursor, &sh.done);
     __syncthreads();
     if (sh.done) return;
     // pass 2: edge records in level order, one thread per row word
@@ -731,7 +753,7 @@ BNS_INLINE void prepare_block(const DepthArgs &A, Ctl *c, int d, SmallSh &sh) {
             e.pB = du - 1;
             e.nA = nA;
             e.n = nA + nB;
-            e.levels = e.n ? 64 - __clzll(e.n) : 0;
+            e.levels = edge_levels(e.n, A.round_width);
             const unsigned int slot = atomicAdd(&sh.cursor[e.levels], 1u);
             A.edges[slot] = e;
             A.min_accept[slot] = ~0ull;
@@ -828,6 +850,10 @@ BNS_INLINE void unrank_lane(const uint64_t *tab, int stride, int rows, int64_t p
     }
 }
 
+BNS_INLINE void decode_edge_rank(const DepthArgs &A, int64_t e, unsigned long long r, const EdgeRec &rec, int d,
+                                 const uint64_t *btab, int bstride, int brows, const ProbDev *probs_lds,
+                                 const uint8_t *cards_lds, Desc &q);
+
 BNS_INLINE void decode_ticket(const DepthArgs &A, const unsigned long long *lvl_base,
                               const unsigned long long *lvl_cnt, int nlev, unsigned long long tk,
                               int d, const uint64_t *btab, int bstride, int brows, bool skip_ok,
@@ -845,12 +871,21 @@ BNS_INLINE void decode_ticket(const DepthArgs &A, const unsigned long long *lvl_
     const unsigned long long jj = ((off | cnt) >> 32) ? off / cnt
                                                       : (unsigned long long)((uint32_t)off / (uint32_t)cnt);
     const int64_t e = (int64_t)(off - jj * cnt);
-    const unsigned long long r = ((1ull << L) - 1ull) + jj;
+    const unsigned long long r =
+        (A.round_width > 0 ? (unsigned long long)L * (unsigned long long)A.round_width : ((1ull << L) - 1ull)) + jj;
     const EdgeRec rec = A.edges[e];
     const unsigned long long ma =
         __hip_atomic_load(&A.min_accept[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     q.valid = (r < rec.n && (!skip_ok || r <= ma)) ? 1 : 0;
     if (!q.valid) return;
+    decode_edge_rank(A, e, r, rec, d, btab, bstride, brows, probs_lds, cards_lds, q);
+}
+
+// The test of rank r of edge e (record rec) at depth d: its columns,
+// cardinalities and sample range (one lane).
+BNS_INLINE void decode_edge_rank(const DepthArgs &A, int64_t e, unsigned long long r, const EdgeRec &rec, int d,
+                                 const uint64_t *btab, int bstride, int brows, const ProbDev *probs_lds,
+                                 const uint8_t *cards_lds, Desc &q) {
     ProbDev P;
     if (probs_lds) P = probs_lds[rec.prob];
     else P = A.probs[rec.prob];
@@ -1278,6 +1313,110 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
 }
 
 // ---------------------------------------------------------------------------
+// Edge-level form (the edge-level parallelism of Section IV-A): a group of
+// lanes (a wave, or a workgroup with test_group 2) takes one edge of the
+// depth at a time and runs its tests in the sequential order until the first
+// accepting one.  No test is speculative, and a group holds an edge for all of
+// its tests, so edges with many tests bound the depth's time.
+// ---------------------------------------------------------------------------
+template <bool GENERAL>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k_depth_edges(DepthArgs A) {
+    extern __shared__ uint32_t lds[];
+    __shared__ TestSh tsh[kWaves];
+    __shared__ Desc slots[kWaves];
+    __shared__ uint64_t btab_lds[kBinomLds];
+    __shared__ ProbDev probs_sh[kProbsLds];
+    __shared__ uint8_t cards_sh[kCardsLds];
+    __shared__ int hdr[4];
+    __shared__ unsigned long long hdr_edges;
+    __shared__ unsigned long long grab[2];
+    __shared__ unsigned long long tal_exec[kWaves], tal_re[kWaves];
+    __shared__ double tal_bytes[kWaves];
+    Ctl *c = A.ctl;
+    const unsigned long long t_enter = wall_clock64();
+    if (threadIdx.x == 0) {
+        hdr[0] = (c->done | c->error) != 0;
+        hdr[1] = c->depth;
+        hdr[2] = c->bstride;
+        hdr[3] = c->brows;
+        hdr_edges = c->n_edges;
+    }
+    if (threadIdx.x < kWaves) {
+        tal_exec[threadIdx.x] = 0;
+        tal_re[threadIdx.x] = 0;
+        tal_bytes[threadIdx.x] = 0.0;
+    }
+    for (int i = threadIdx.x; i < kBinomLds; i += kWG) btab_lds[i] = c->bslice[i];
+    const bool probs_in_lds = A.n_probs <= kProbsLds;
+    const bool cards_in_lds = A.n_globals <= kCardsLds;
+    if (probs_in_lds && threadIdx.x < (unsigned)A.n_probs) probs_sh[threadIdx.x] = A.probs[threadIdx.x];
+    if (cards_in_lds)
+        for (int i = threadIdx.x; i < A.n_globals; i += kWG) cards_sh[i] = A.cards[i];
+    __syncthreads();
+    if (uni(hdr[0])) return;
+    const int d = uni(hdr[1]);
+    const unsigned long long E = uni(hdr_edges);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && d < kMaxDepths) c->stats[d].t_start = t_enter;
+    const uint64_t *btab = A.binom;
+    int bstride = kBinomK, brows = A.binom_rows;
+    if (uni(hdr[2]) > 0) {
+        btab = btab_lds;
+        bstride = uni(hdr[2]);
+        brows = uni(hdr[3]);
+    }
+    const int w = uni((int)(threadIdx.x >> 6));
+    const int mode = A.mode_policy == 2 ? 1 : 0;  // one wave per edge unless a workgroup is asked for
+    const Grp g = mode ? Grp::workgroup() : Grp::wave();
+    TestSh &t = tsh[mode ? 0 : w];
+    Desc &q = slots[mode ? 0 : w];
+    const uint32_t W = mode ? (uint32_t)A.tile.lds_words : (uint32_t)A.tile.lds_words / kWaves;
+    uint32_t *region = mode ? lds : lds + (uint32_t)w * W;
+    const int ti = mode ? 0 : w;
+    for (;;) {
+        unsigned long long e = 0, z = 0;
+        if (g.rank == 0) e = atomicAdd(&c->grab_ctr[0], 1ull);
+        group_bcast2_u64(g, e, z, grab);
+        e = uni(e);
+        if (e >= E) break;
+        const EdgeRec rec = A.edges[e];
+        const unsigned long long n = uni((unsigned long long)rec.n);
+        for (unsigned long long r = 0; r < n; ++r) {
+            if (g.rank == 0)
+                decode_edge_rank(A, (int64_t)e, r, rec, d, btab, bstride, brows, probs_in_lds ? probs_sh : nullptr,
+                                 cards_in_lds ? cards_sh : nullptr, q);
+            g.sync();
+            stage_test(g, q, t);
+            const int64_t qm = uni(q.m);
+            const TestOut o = run_test<false, GENERAL>(g, t, region, W, A.tile, uni(q.alpha), nullptr,
+                                                       Src{nullptr, nullptr, 0, qm});
+            const bool accepted = (uni((uint32_t)o.flags) & 1u) != 0;
+            if (g.rank == 0) {
+                ++tal_exec[ti];
+                if (o.flags & 2) ++tal_re[ti];
+                tal_bytes[ti] += (double)q.ncols * (double)qm;
+                if (o.err) c->error = o.err;
+                if (accepted) atomicMin(&A.min_accept[e], r);
+                if (A.per_prob) {
+                    __hip_atomic_fetch_add(&A.ecnt[2 * e], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (o.flags & 2)
+                        __hip_atomic_fetch_add(&A.ecnt[2 * e + 1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            g.sync();
+            if (accepted || o.err) break;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kWaves && d < kMaxDepths) {
+        const int k = threadIdx.x;
+        if (tal_exec[k]) atomicAdd(&c->stats[d].executed, tal_exec[k]);
+        if (tal_re[k]) atomicAdd(&c->stats[d].rechecks, tal_re[k]);
+        if (tal_bytes[k] > 0.0) atomicAdd(&c->stats[d].operand_bytes, tal_bytes[k]);
+        if (k == 0) atomicMax(&c->stats[d].t_end, (unsigned long long)wall_clock64());
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Depth completion: remove accepted edges, record sepsets and the canonical
 // test count (per edge: ranks up to and including its first accepting one).
 // The last block to finish advances the control block to the next depth.
@@ -1593,11 +1732,12 @@ static auto depth_tests_kernel(const DepthArgs &a) -> decltype(&k_depth_tests<0,
 
 hipError_t launch_depth_tests(const DepthArgs &a, int grid, hipStream_t s, hipEvent_t start,
                               hipEvent_t stop) {
+    auto kern = depth_tests_kernel(a);
+    if (a.edge_form) kern = (a.tile.stat != 0 || a.tile.df_rule != 0) ? &k_depth_edges<true> : &k_depth_edges<false>;
     if (start && stop)
-        hipExtLaunchKernelGGL(depth_tests_kernel(a), dim3(grid), dim3(kWG), (size_t)a.tile.lds_words * 4u, s,
-                              start, stop, 0, a);
+        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kWG), (size_t)a.tile.lds_words * 4u, s, start, stop, 0, a);
     else
-        hipLaunchKernelGGL(depth_tests_kernel(a), dim3(grid), dim3(kWG), (size_t)a.tile.lds_words * 4u, s, a);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kWG), (size_t)a.tile.lds_words * 4u, s, a);
     return hipGetLastError();
 }
 
@@ -1610,7 +1750,8 @@ hipError_t launch_depth_apply(const DepthArgs &a, hipStream_t s) {
 hipError_t allow_dynamic_lds(int bytes) {
     const void *fns[] = {(const void *)k_depth_tests<kGrabRunLog2, false, false>,
                          (const void *)k_depth_tests<0, false, false>, (const void *)k_depth_tests<0, true, false>,
-                         (const void *)k_depth_tests<0, false, true>, (const void *)k_depth_tests<0, true, true>};
+                         (const void *)k_depth_tests<0, false, true>, (const void *)k_depth_tests<0, true, true>,
+                         (const void *)k_depth_edges<false>, (const void *)k_depth_edges<true>};
     hipError_t e = hipSuccess;
     for (const void *f : fns)
         if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);

@@ -39,7 +39,7 @@ def test_options_defaults(bns):
     assert o.precision == bns.BNS_PREC_FP32_RECHECK
     assert o.recheck_band == 1e-3
     assert o.use_graph == 1 and o.timing == 0
-    assert o.wave_depths == 0 and o.block_depths == 0 and list(o.reserved) == [0, 0, 0]
+    assert o.wave_depths == 0 and o.block_depths == 0 and list(o.reserved) == [0, 0] and o.round_tests == 0
     assert o.report_errors == 0 and o.workspace_mb == 0
     assert o.statistic == bns.BNS_STAT_G2 and o.df_rule == bns.BNS_DF_DECLARED
     assert o.depth0 == bns.BNS_DEPTH0_AUTO
@@ -81,7 +81,8 @@ def test_bad_options_rejected(bns):
                 dict(ticket_runs=3), dict(ticket_runs=-1),
                 dict(wave_depths=0b110, block_depths=0b011), dict(report_errors=2),
                 dict(report_errors=-1), dict(workspace_mb=-1), dict(statistic=2), dict(statistic=-1),
-                dict(df_rule=2), dict(depth0=3), dict(depth0=-1)):
+                dict(df_rule=2), dict(depth0=3), dict(depth0=-1), dict(round_tests=-1),
+                dict(round_tests=65537), dict(form=3)):
         o = bns.bns_options_default(**bad)
         with pytest.raises(bns.BnsError, match="options"):
             bns.bns_pc_skeleton(np.zeros((3, 10), np.uint8), np.array([2, 2, 2], np.uint8),
