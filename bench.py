@@ -200,6 +200,56 @@ def check_parity(sks, config):
     return True, "identical to the oracle"
 
 
+def study(bns, torch, handles, dss, alphas, maxd, config, steps, warmup, with_plain):
+    """Granularity and level-width study (Sections IV-A and IV-B): the same
+    workload through the sample-level form (plain, one sample-parallel launch
+    per test), the edge-level form (one group per edge) and the CI-level
+    batched form, then the batched form with levels of g ranks per edge.  Per
+    row: ms per search (median of the timed searches), canonical CI tests per
+    second, and the extra-tests proportion (executed / required - 1)."""
+    import statistics
+
+    def timed(o, n_steps, n_warm):
+        def run():
+            if len(handles) == 1:
+                return [bns.skeleton_handle(handles[0], alphas[0], maxd[0], o)]
+            return bns.skeleton_batch_handles(handles, alphas, maxd, o)
+        for _ in range(n_warm):
+            for h in run():
+                bns.free_skeleton(h)
+        torch.cuda.synchronize()
+        ts, sks = [], None
+        for _ in range(n_steps):
+            t0 = time.perf_counter()
+            hs = run()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            cur = [bns.collect(h) for h in hs]
+            sks = sks or cur
+        tot = depth_totals(sks)
+        req, ex = _sum(tot, "tests_required"), _sum(tot, "tests_executed")
+        ok, _ = check_parity(sks, config)
+        ms = 1e3 * statistics.median(ts)
+        return {"ms_per_search": ms, "ci_tests_per_s": req / (ms * 1e-3), "tests_required": req,
+                "tests_executed": ex, "extra_tests": ex / req - 1.0, "parity": ok}
+
+    rows = []
+    forms = [("batched (CI-level)", dict()), ("edge-level, wave per edge", dict(form=bns.BNS_FORM_EDGE)),
+             ("edge-level, workgroup per edge", dict(form=bns.BNS_FORM_EDGE, test_group=2))]
+    if with_plain:
+        forms.append(("plain (sample-level)", dict(form=bns.BNS_FORM_PLAIN, precision=1)))
+    for name, kw in forms:
+        plain = kw.get("form") == bns.BNS_FORM_PLAIN
+        r = timed(bns.bns_options_default(**kw), 1 if plain else steps, 0 if plain else warmup)
+        rows.append(dict(study="granularity", form=name, **r))
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    for g in (0, 1, 2, 4, 6, 8, 10, 16, 32):
+        r = timed(bns.bns_options_default(round_tests=g), steps, warmup)
+        rows.append(dict(study="level width", round_tests=g, **r))
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,6 +276,9 @@ def main():
     ap.add_argument("--no-stream-peak", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the given options instead of the autotuned ones")
+    ap.add_argument("--study", action="store_true",
+                    help="granularity (plain / edge-level / batched) and level-width study instead of the "
+                         "benchmark line")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (profiler byte calibration)")
     a = ap.parse_args()
@@ -258,6 +311,11 @@ def main():
     handles = [bns.bns_dataset_create(d.data, d.cards) for d in dss]
     alphas = [d.alpha for d in dss]
     maxd = [d.max_depth for d in dss]
+    if a.study:
+        rows = study(bns, torch, handles, dss, alphas, maxd, a.config, a.steps, a.warmup,
+                     with_plain=not a.no_plain and len(dss) == 1 and a.config <= 2)
+        print(json.dumps({"workload": CONFIGS[a.config]["name"], "rows": rows}), flush=True)
+        return
     knobs = dict(precision=a.precision, lds_bytes=a.lds_bytes, wg_per_cu=a.wg_per_cu,
                  split_min_samples=a.split_min, units_per_group=a.units_per_group,
                  test_group=a.test_group, max_replicas=a.max_replicas,
