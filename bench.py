@@ -46,6 +46,8 @@ def depth_totals(sks):
         t["depth"] = d
         t["span_seconds"] = rows[0]["span_seconds"]
         t["kernel_seconds"] = rows[0]["kernel_seconds"]
+        for k in ("test_group", "chunks", "chunk_samples"):  # launch shape, shared
+            t[k] = rows[0].get(k, 0)
         out.append(t)
     return out
 
@@ -113,19 +115,21 @@ def measured_traffic(workload):
 
 
 def streaming_read_peak_gbs(torch, gib=4, reps=10):
-    """Device read bandwidth of this machine: a reduction over a buffer far larger
-    than the last-level cache (GB/s, best of reps)."""
+    """Device read bandwidth of this machine: float reductions (sum, max) over a
+    buffer far larger than the last-level cache (GB/s, best of reps and of
+    the two reductions)."""
     n = gib << 30
-    x = torch.ones(n // 4, dtype=torch.int32, device="cuda")
+    x = torch.ones(n // 4, dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
     best = 0.0
-    for _ in range(reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        s = torch.sum(x, dtype=torch.int64)
-        e1.record()
-        e1.synchronize()
-        best = max(best, n / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    for op in (torch.sum, torch.amax):
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            s = op(x)
+            e1.record()
+            e1.synchronize()
+            best = max(best, n / (e0.elapsed_time(e1) * 1e-3) / 1e9)
     del s, x
     torch.cuda.empty_cache()
     return best
@@ -396,6 +400,8 @@ def main():
             "tests_executed": tot[d]["tests_executed"],
             "alu_frac": (req_bytes_d[d] / sd) / ALU_LANE_OPS_PER_S if sd > 0 else None,
             "operand_gbs_required": req_bytes_d[d] / sd / 1e9 if sd > 0 else None,
+            "lanes_per_test": {1: "wave", 2: "workgroup", 3: "pair contraction"}.get(tot[d]["test_group"]),
+            "chunks": tot[d]["chunks"], "chunk_samples": tot[d]["chunk_samples"],
         })
     stream_peak = None if a.no_stream_peak else streaming_read_peak_gbs(torch)
 

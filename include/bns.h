@@ -265,7 +265,9 @@ typedef struct bns_skeleton bns_skeleton;
 /* Per-depth counters of a skeleton search. */
 typedef struct bns_depth_stats {
     int32_t depth;
-    int32_t reserved;
+    int32_t test_group;      /* batched form: lanes per test at this depth, 1 = one wave,
+                                2 = one workgroup, 3 = depth 0 ran as the pair contraction
+                                (bns_ci_pairs' tables); 0 in the plain form */
     int64_t edges;           /* edges alive when the depth started */
     int64_t tests_required;  /* tests in the canonical sequential order: per edge, up to
                                 and including its first accepting test */
@@ -286,6 +288,12 @@ typedef struct bns_depth_stats {
     double err_max;          /* largest relative FP32 error of the statistic */
     double err_p50;          /* median */
     double err_p99;          /* 99th percentile */
+    /* Samples per work unit at this depth (0 in the plain form): */
+    int32_t chunks;          /* sample chunks each test was cut into (1: not split; 0 for
+                                the pair contraction) */
+    int32_t reserved;
+    int64_t chunk_samples;   /* samples per chunk (the longest dataset's count when not
+                                split; the pair contraction's sample chunk) */
 } bns_depth_stats;
 
 /* Learns the skeleton of one dataset.  alpha in (0, 1); max_depth >= -1
@@ -306,18 +314,26 @@ bns_status bns_pc_skeleton_batch(const bns_dataset *const *ds, int32_t n_problem
                                  const double *alpha, const int32_t *max_depth,
                                  const bns_options *opt, bns_skeleton **outs);
 
-/* Chooses launch options for the batched search of these datasets (the tile
- * shape of the per-depth test kernel: lanes per test, LDS budget and table
- * replication, tests per grab) by timing complete trial searches, each
- * candidate measured `trials` times (median; 0 = 5).  Unless base fixes the
- * lanes per test, they are first chosen per depth (wave_depths /
- * block_depths) from the depth spans of trial searches with one wave and with
- * one workgroup per test; then every combination of the other options that
- * base leaves open (at most 27); then the per-depth choice again under them.
- * Each choice is kept only if the whole search gets faster.  *best receives base with the fastest choices filled in
- * (base NULL = defaults).  The choice is cached per device and workload
- * (problem sizes, alphas, max depths), so repeated calls return at once.
- * The trial searches run on the device like bns_pc_skeleton_batch. */
+/* Chooses launch options for the batched search of these datasets by timing
+ * complete trial searches, each candidate measured `trials` times (median;
+ * 0 = 5).  Searched, each only where base leaves it open (0 / AUTO):
+ *   1. lanes per test, per depth (wave_depths / block_depths), from the depth
+ *      spans of trial searches with one wave and one workgroup per test;
+ *   2. every combination of replication cap, LDS budget and tests per grab
+ *      (a grid of at most 27), then step 1 again under the chosen options;
+ *   3. samples per work unit: split_min_samples in {default, 2048, 8192,
+ *      16384, never} x units_per_group in {default, 4, 16};
+ *   4. the depth-0 path (the test kernel or the pair contraction).
+ * A candidate is kept only if the whole search gets clearly faster.  *best
+ * receives base with the chosen options filled in (base NULL = defaults).
+ * The choice is cached per device (architecture and compute units) and
+ * workload (problem sizes, alphas, max depths, precision, statistic, the
+ * options base fixes): in memory, and appended to a text file that later
+ * processes read: $BNS_TUNE_CACHE if set, else $XDG_CACHE_HOME/bns_autotune.txt,
+ * else $HOME/.cache/bns_autotune.txt; a file that cannot be read or written
+ * is skipped silently (options never change results).  Repeated calls for a
+ * cached workload return at once.  The trial searches run on the device like
+ * bns_pc_skeleton_batch. */
 bns_status bns_autotune(const bns_dataset *const *ds, int32_t n_problems, const double *alpha,
                         const int32_t *max_depth, const bns_options *base, int32_t trials,
                         bns_options *best);

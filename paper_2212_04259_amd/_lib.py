@@ -67,14 +67,16 @@ class bns_ci_test(ctypes.Structure):
 
 
 class bns_depth_stats(ctypes.Structure):
-    _fields_ = [("depth", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    _fields_ = [("depth", ctypes.c_int32), ("test_group", ctypes.c_int32),
                 ("edges", ctypes.c_int64), ("tests_required", ctypes.c_int64),
                 ("tests_executed", ctypes.c_int64), ("removed", ctypes.c_int64),
                 ("rechecks", ctypes.c_int64), ("tickets", ctypes.c_int64),
                 ("operand_bytes", ctypes.c_double), ("kernel_seconds", ctypes.c_double),
                 ("span_seconds", ctypes.c_double), ("err_tests", ctypes.c_int64),
                 ("err_flips", ctypes.c_int64), ("err_max", ctypes.c_double),
-                ("err_p50", ctypes.c_double), ("err_p99", ctypes.c_double)]
+                ("err_p50", ctypes.c_double), ("err_p99", ctypes.c_double),
+                ("chunks", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("chunk_samples", ctypes.c_int64)]
 
 
 _lib = None

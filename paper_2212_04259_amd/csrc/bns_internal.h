@@ -63,6 +63,9 @@ struct DepthStatDev {
     double operand_bytes;
     unsigned long long t_start;      // entry of the test kernel's workgroup 0, 100 MHz device clock
     unsigned long long t_end;        // latest workgroup end
+    int32_t mode;                    // 0 one test per wave, 1 per workgroup
+    int32_t chunks;                  // sample chunks per test (1: not split)
+    long long chunk_len;             // samples per chunk
 };
 
 // Per-problem, per-depth counters of a multi-dataset search (problem k,

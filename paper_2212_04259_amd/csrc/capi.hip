@@ -8,9 +8,12 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <memory>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -142,7 +145,12 @@ struct GraphEntry {
     bool init = false;  // begins with the search's initialisation
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;  // recorded after each replay
     ~GraphEntry() {
+        if (done) {
+            (void)hipEventSynchronize(done);
+            (void)hipEventDestroy(done);
+        }
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
     }
@@ -879,11 +887,19 @@ static const size_t kSpecPoolWords = 64u << 10;
 // the same graph serves every starting depth.
 static bns_status depth_graph(DevCtx &dc, const DepthArgs &a, int grid, int K, bool init, hipStream_t s,
                               GraphEntry **out) {
-    for (auto &g : dc.graphs)
+    for (size_t i = 0; i < dc.graphs.size(); ++i) {
+        GraphEntry *g = dc.graphs[i].get();
         if (g->K == K && g->grid == grid && g->init == init && std::memcmp(&g->args, &a, sizeof(a)) == 0) {
-            *out = g.get();
+            // most recently used last: eviction takes the front
+            std::rotate(dc.graphs.begin() + i, dc.graphs.begin() + i + 1, dc.graphs.end());
+            *out = g;
             return BNS_OK;
         }
+    }
+    // the least recently used graph goes; its destructor waits for its last
+    // replay (the host returns once the completion flag is up, before the
+    // graph has ended)
+    if (dc.graphs.size() >= 8) dc.graphs.erase(dc.graphs.begin());
     std::unique_ptr<GraphEntry> g(new GraphEntry());
     g->args = a;
     g->grid = grid;
@@ -901,7 +917,7 @@ static bns_status depth_graph(DevCtx &dc, const DepthArgs &a, int grid, int K, b
     HIP_TRY(e);
     HIP_TRY(e2);
     HIP_TRY(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
-    if (dc.graphs.size() >= 8) dc.graphs.erase(dc.graphs.begin());
+    HIP_TRY(hipEventCreateWithFlags(&g->done, hipEventDisableTiming));
     *out = g.get();
     dc.graphs.push_back(std::move(g));
     return BNS_OK;
@@ -1206,6 +1222,7 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
             st = depth_graph(dc, a, grid, K, d == 0, s, &ge);
             if (st != BNS_OK) return st;
             HIP_TRY(hipGraphLaunch(ge->exec, s));
+            HIP_TRY(hipEventRecord(ge->done, s));
         } else {
             if (d == 0) HIP_TRY(launch_init_search(a, s));
             for (int i = 0; i < K; ++i) {
@@ -1251,6 +1268,9 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
             r.rechecks = (int64_t)sd.rechecks;
             r.tickets = (int64_t)sd.tickets;
             r.operand_bytes = sd.operand_bytes;
+            r.test_group = sd.mode + 1;
+            r.chunks = sd.chunks;
+            r.chunk_samples = sd.chunk_len;
             if (sd.t_end && sd.t_start) {
                 const unsigned long long t0 = sd.t_start;
                 if (sd.t_end > t0) r.span_seconds = (double)(sd.t_end - t0) / (1e3 * dc.wall_khz);
@@ -1571,12 +1591,77 @@ extern "C" bns_status bns_pc_skeleton_batch(const bns_dataset *const *ds, int32_
 // Autotuning of the batched search's launch options
 // ---------------------------------------------------------------------------
 struct TuneEntry {
-    int device;
+    std::string device;  // architecture and compute units
     std::vector<int64_t> key;
     bns_options best;
 };
 static std::mutex g_tune_mu;
 static std::vector<TuneEntry> g_tune;
+static bool g_tune_loaded = false;
+
+// The tuned options that are kept (stream excluded), in file order.
+static int32_t *tune_field(bns_options &o, int i) {
+    int32_t *f[] = {&o.test_group, &o.max_replicas, &o.lds_bytes, &o.tickets_per_grab, &o.split_min_samples,
+                    &o.units_per_group, &o.depth0, &o.round_tests, (int32_t *)&o.wave_depths,
+                    (int32_t *)&o.block_depths};
+    return i < 10 ? f[i] : nullptr;
+}
+
+// Persistent cache of tuned options: the file named by BNS_TUNE_CACHE, else
+// $XDG_CACHE_HOME/bns_autotune.txt, else $HOME/.cache/bns_autotune.txt (no
+// file when none is set).  One line per entry:
+//   bns2 <device> <key, comma-separated> <ten option values>
+// Unreadable or malformed lines are ignored; the file is only a shortcut
+// (options never change results).
+static std::string tune_path() {
+    if (const char *p = std::getenv("BNS_TUNE_CACHE")) return p;
+    if (const char *x = std::getenv("XDG_CACHE_HOME")) return std::string(x) + "/bns_autotune.txt";
+    if (const char *h = std::getenv("HOME")) return std::string(h) + "/.cache/bns_autotune.txt";
+    return "";
+}
+
+static void tune_load_file() {
+    g_tune_loaded = true;
+    const std::string path = tune_path();
+    if (path.empty()) return;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream in(line);
+        std::string tag, dev, keys;
+        if (!(in >> tag >> dev >> keys) || tag != "bns2") continue;
+        TuneEntry e;
+        e.device = dev;
+        bool ok = true;
+        std::istringstream ks(keys);
+        for (std::string tok; ok && std::getline(ks, tok, ',');) {
+            char *end = nullptr;
+            e.key.push_back(std::strtoll(tok.c_str(), &end, 10));
+            ok = !tok.empty() && *end == '\0';
+        }
+        bns_options_default(&e.best);
+        for (int i = 0; i < 10 && ok; ++i) {
+            long long v = 0;
+            if (!(in >> v)) ok = false;
+            else *tune_field(e.best, i) = (int32_t)v;
+        }
+        bns_options checked;
+        if (ok && read_options(&e.best, &checked) == BNS_OK) g_tune.push_back(e);
+    }
+}
+
+static void tune_save_entry(const TuneEntry &e) {
+    const std::string path = tune_path();
+    if (path.empty()) return;
+    FILE *f = std::fopen(path.c_str(), "a");
+    if (!f) return;  // a cache that cannot be written is not an error
+    std::fprintf(f, "bns2 %s ", e.device.c_str());
+    for (size_t i = 0; i < e.key.size(); ++i) std::fprintf(f, "%s%lld", i ? "," : "", (long long)e.key[i]);
+    bns_options o = e.best;
+    for (int i = 0; i < 10; ++i) std::fprintf(f, " %d", *tune_field(o, i));
+    std::fprintf(f, "\n");
+    std::fclose(f);
+}
 
 extern "C" bns_status bns_autotune(const bns_dataset *const *ds, int32_t n_problems,
                                    const double *alpha, const int32_t *max_depth,
@@ -1599,12 +1684,28 @@ extern "C" bns_status bns_autotune(const bns_dataset *const *ds, int32_t n_probl
         std::memcpy(&ab, &alpha[k], sizeof(ab));
         key.insert(key.end(), {ds[k]->n, ds[k]->m, ab, max_depth[k]});
     }
-    const int device = ds[0]->device;
+    std::string device;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, ds[0]->device) != hipSuccess)
+            return fail(BNS_E_DEVICE, "cannot read the properties of device %d", ds[0]->device);
+        char buf[160];
+        std::snprintf(buf, sizeof(buf), "%s/%dcu", prop.gcnArchName, prop.multiProcessorCount);
+        for (char *c = buf; *c; ++c)
+            if (*c == ' ') *c = '_';
+        device = buf;
+    }
+    // options that base fixes are part of the key
+    for (int i = 0; i < 10; ++i) key.push_back(*tune_field(o, i));
+    key.push_back(o.statistic);
+    key.push_back(o.df_rule);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (!g_tune_loaded) tune_load_file();
         for (const TuneEntry &e : g_tune)
             if (e.device == device && e.key == key) {
-                *best = e.best;
+                *best = o;
+                for (int i = 0; i < 10; ++i) *tune_field(*best, i) = *tune_field(const_cast<bns_options &>(e.best), i);
                 best->stream = o.stream;
                 return BNS_OK;
             }
@@ -1711,9 +1812,48 @@ extern "C" bns_status bns_autotune(const bns_dataset *const *ds, int32_t n_probl
     }
     st = try_depths();
     if (st != BNS_OK) return st;
+    // Samples per work unit: a depth with too few tests to fill the device
+    // cuts each test's samples into chunks counted by different groups; the
+    // smallest chunk and the units aimed for per group set how far.
+    if (!o.split_min_samples && !o.units_per_group) {
+        const int32_t split_opts[] = {0, 2048, 8192, 16384, -1};
+        const int32_t upg_opts[] = {0, 4, 16};
+        const bns_options start2 = cur;
+        for (int32_t sm : split_opts)
+            for (int32_t up : upg_opts) {
+                if (sm == -1 && up) continue;
+                bns_options c = start2;
+                c.split_min_samples = sm;
+                c.units_per_group = up;
+                if (std::memcmp(&c, &cur, sizeof(c)) == 0) continue;
+                double t = 0.0;
+                st = timed(c, &t);
+                if (st != BNS_OK) return st;
+                if (t < cur_t * 0.98) {
+                    cur = c;
+                    cur_t = t;
+                }
+            }
+    }
+    // Depth 0 in the test kernel or through the pair contraction.
+    if (o.depth0 == BNS_DEPTH0_AUTO) {
+        for (int32_t d0 : {BNS_DEPTH0_TESTS, BNS_DEPTH0_PAIRS}) {
+            bns_options c = cur;
+            c.depth0 = d0;
+            double t = 0.0;
+            st = timed(c, &t);
+            if (st == BNS_E_NOMEM && d0 == BNS_DEPTH0_PAIRS) continue;  // tiles beyond the limit
+            if (st != BNS_OK) return st;
+            if (t < cur_t * 0.98) {
+                cur = c;
+                cur_t = t;
+            }
+        }
+    }
     *best = cur;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune.push_back(TuneEntry{device, key, cur});
+    tune_save_entry(g_tune.back());
     return BNS_OK;
 }
 

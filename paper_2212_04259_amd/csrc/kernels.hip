@@ -445,6 +445,9 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
         } else if (d < kMaxDepths) {
             c->stats[d].edges = c->n_edges;
             c->stats[d].tickets = total;
+            c->stats[d].mode = mode;
+            c->stats[d].chunks = (int32_t)C;
+            c->stats[d].chunk_len = Lc;
         }
     }
 }

@@ -67,7 +67,12 @@ __global__ __launch_bounds__(kGramWG) void k_gram(PairArgs P, Ctl *c) {
     __shared__ int quit;
     if (threadIdx.x == 0) {
         quit = c ? c->done : 0;
-        if (c && blockIdx.x == 0) c->stats[0].t_start = wall_clock64();
+        if (c && blockIdx.x == 0) {
+            c->stats[0].t_start = wall_clock64();
+            c->stats[0].mode = 2;  // depth 0 as the pair contraction
+            c->stats[0].chunks = 0;
+            c->stats[0].chunk_len = P.chunk;
+        }
     }
     __syncthreads();
     if (quit) return;

@@ -18,3 +18,12 @@ def orc():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _private_tune_cache(tmp_path_factory):
+    # the autotuner appends its choices to a file; tests keep theirs apart
+    # from the user's cache
+    if "BNS_TUNE_CACHE" not in os.environ:
+        os.environ["BNS_TUNE_CACHE"] = str(tmp_path_factory.mktemp("tune") / "bns_autotune.txt")
+    yield
