@@ -274,6 +274,7 @@ def main():
     ap.add_argument("--block-depths", type=int, default=0,
                     help="bit d set: one workgroup per test at depth d")
     ap.add_argument("--depth0", type=int, default=0, help="0 auto, 1 test kernel, 2 pair tables")
+    ap.add_argument("--depth1", type=int, default=0, help="0 auto, 1 test kernel, 2 masked Gram tables")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
@@ -324,7 +325,7 @@ def main():
                  split_min_samples=a.split_min, units_per_group=a.units_per_group,
                  test_group=a.test_group, max_replicas=a.max_replicas,
                  tickets_per_grab=a.tickets_per_grab, wave_depths=a.wave_depths,
-                 block_depths=a.block_depths, depth0=a.depth0)
+                 block_depths=a.block_depths, depth0=a.depth0, depth1=a.depth1)
     opt = bns.bns_options_default(**knobs)
     tuned = None
     if not a.no_autotune:
@@ -332,7 +333,7 @@ def main():
         opt = bns.bns_autotune(handles, alphas, maxd, opt)
         tuned = {f: getattr(opt, f) for f in ("test_group", "max_replicas", "lds_bytes",
                                                "tickets_per_grab", "wave_depths", "block_depths",
-                                               "split_min_samples", "units_per_group", "depth0")}
+                                               "split_min_samples", "units_per_group", "depth0", "depth1")}
         knobs.update(tuned)
 
     def step(o):
@@ -400,7 +401,7 @@ def main():
             "tests_executed": tot[d]["tests_executed"],
             "alu_frac": (req_bytes_d[d] / sd) / ALU_LANE_OPS_PER_S if sd > 0 else None,
             "operand_gbs_required": req_bytes_d[d] / sd / 1e9 if sd > 0 else None,
-            "lanes_per_test": {1: "wave", 2: "workgroup", 3: "pair contraction"}.get(tot[d]["test_group"]),
+            "lanes_per_test": {1: "wave", 2: "workgroup", 3: "Gram contraction"}.get(tot[d]["test_group"]),
             "chunks": tot[d]["chunks"], "chunk_samples": tot[d]["chunk_samples"],
         })
     stream_peak = None if a.no_stream_peak else streaming_read_peak_gbs(torch)

@@ -136,7 +136,9 @@ typedef struct bns_options {
                               levels takes the rest).  A test whose edge has accepted at a
                               lower rank is skipped when it is taken; those run before the
                               accept was seen count as executed (speculative) tests */
-    int32_t reserved[2];   /* must be zero */
+    int32_t depth1;        /* batched form, depth 1 (conditioning sets of one variable):
+                              BNS_DEPTH1_* (default automatic) */
+    int32_t reserved;      /* must be zero */
     void *stream;          /* hipStream_t; NULL = default stream */
 } bns_options;
 
@@ -165,6 +167,22 @@ enum {
                                columns (Section IV-B: depth 0 tests every pair); the
                                statistic is evaluated in FP64.  Verification mode
                                (report_errors) keeps depth 0 in the test kernel */
+};
+
+/* Depth-1 path of the batched form. */
+enum {
+    BNS_DEPTH1_AUTO = 0,    /* TESTS (the contraction evaluates every depth-1 test, where the
+                               sequential order stops an edge at its first accepting test:
+                               measured slower on all five benchmark workloads) */
+    BNS_DEPTH1_TESTS = 1,   /* the depth's tests run in the per-depth test kernel */
+    BNS_DEPTH1_GRAM = 2     /* every depth-1 table as a block of masked Gram matrices: for
+                               each node u and category c of u, the one-hot columns of u's
+                               frozen neighbours multiplied over the samples with X_u = c
+                               (int8 MFMA, exact counts); every depth-1 test is evaluated,
+                               in FP64, and each edge keeps its first accepting test, so the
+                               results are those of Algorithm 1.  Needs cardinalities in [2, 8];
+                               otherwise, in verification mode, in the edge-level form, or
+                               when the plan exceeds the tile buffer, the test kernel runs */
 };
 
 /* Fills *opt with the defaults.  opt must not be NULL. */
@@ -323,7 +341,8 @@ bns_status bns_pc_skeleton_batch(const bns_dataset *const *ds, int32_t n_problem
  *      (a grid of at most 27), then step 1 again under the chosen options;
  *   3. samples per work unit: split_min_samples in {default, 2048, 8192,
  *      16384, never} x units_per_group in {default, 4, 16};
- *   4. the depth-0 path (the test kernel or the pair contraction).
+ *   4. the depth-1 path (the test kernel or the masked contractions);
+ *   5. the depth-0 path (the test kernel or the pair contraction).
  * A candidate is kept only if the whole search gets clearly faster.  *best
  * receives base with the chosen options filled in (base NULL = defaults).
  * The choice is cached per device (architecture and compute units) and

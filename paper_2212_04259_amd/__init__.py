@@ -12,6 +12,9 @@ from ._lib import (  # noqa: F401
     BNS_DEPTH0_AUTO,
     BNS_DEPTH0_PAIRS,
     BNS_DEPTH0_TESTS,
+    BNS_DEPTH1_AUTO,
+    BNS_DEPTH1_GRAM,
+    BNS_DEPTH1_TESTS,
     BNS_DF_ADJUSTED,
     BNS_DF_DECLARED,
     BNS_FORM_BATCHED,

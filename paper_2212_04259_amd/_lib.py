@@ -24,6 +24,7 @@ BNS_CI_INDEPENDENT, BNS_CI_RECHECKED = 1, 2
 BNS_STAT_G2, BNS_STAT_X2 = 0, 1
 BNS_DF_DECLARED, BNS_DF_ADJUSTED = 0, 1
 BNS_DEPTH0_AUTO, BNS_DEPTH0_TESTS, BNS_DEPTH0_PAIRS = 0, 1, 2
+BNS_DEPTH1_AUTO, BNS_DEPTH1_TESTS, BNS_DEPTH1_GRAM = 0, 1, 2
 STATUS_NAMES = {0: "BNS_OK", 1: "BNS_E_INVALID_ARG", 2: "BNS_E_VALUE_RANGE",
                 3: "BNS_E_TABLE_TOO_LARGE", 4: "BNS_E_NOMEM", 5: "BNS_E_DEVICE",
                 6: "BNS_E_INTERNAL"}
@@ -57,7 +58,8 @@ class bns_options(ctypes.Structure):
                 ("block_depths", ctypes.c_uint32), ("report_errors", ctypes.c_int32),
                 ("workspace_mb", ctypes.c_int32), ("statistic", ctypes.c_int32),
                 ("df_rule", ctypes.c_int32), ("depth0", ctypes.c_int32),
-                ("round_tests", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
+                ("round_tests", ctypes.c_int32), ("depth1", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
 
 

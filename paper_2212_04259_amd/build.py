@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbns.so")
-SOURCES = ["capi.hip", "kernels.hip", "pairs.hip", "orient.cpp"]
+SOURCES = ["capi.hip", "kernels.hip", "pairs.hip", "triples.hip", "orient.cpp"]
 ARCH = "gfx950"
 
 

@@ -97,6 +97,15 @@ struct Ctl {
     unsigned long long total_units;    // total_tickets * chunks
     long long chunk_len;               // samples per chunk (a multiple of 1024)
     unsigned long long split_cap;      // cells of each ticket's merge table
+    // Depth 1 through the masked Gram contractions: the depth whose tests
+    // the contraction ran (-1: none), its work items, (tile, category group)
+    // pairs, the longest chunk count of a node and the samples per chunk.
+    int32_t gram_depth;
+    int32_t tri_nch_max;
+    unsigned long long tri_items;
+    unsigned long long tri_base;
+    unsigned long long tri_tests;
+    long long tri_chunk;
     unsigned long long level_base[kMaxLevels + 1];
     unsigned long long level_cnt[kMaxLevels + 1];
     unsigned int hist[kMaxLevels + 2];

@@ -106,8 +106,9 @@ static bns_status read_options(const bns_options *in, bns_options *out) {
         return fail(BNS_E_INVALID_ARG, "options.depth0 must be a BNS_DEPTH0_* value");
     if (out->round_tests < 0 || out->round_tests > 65536)
         return fail(BNS_E_INVALID_ARG, "options.round_tests must be in [0, 65536]");
-    for (int i = 0; i < 2; ++i)
-        if (out->reserved[i] != 0) return fail(BNS_E_INVALID_ARG, "options.reserved must be zero");
+    if (out->depth1 < BNS_DEPTH1_AUTO || out->depth1 > BNS_DEPTH1_GRAM)
+        return fail(BNS_E_INVALID_ARG, "options.depth1 must be a BNS_DEPTH1_* value");
+    if (out->reserved != 0) return fail(BNS_E_INVALID_ARG, "options.reserved must be zero");
     return BNS_OK;
 }
 
@@ -143,6 +144,7 @@ struct GraphEntry {
     int grid = 0;
     int K = 0;
     bool init = false;  // begins with the search's initialisation
+    int tri_seq = -1;   // depth sequence that runs depth 1 through the Gram contraction
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;  // recorded after each replay
@@ -167,6 +169,7 @@ struct DevCtx {
     DevBuf setup, adj, adjbits, nbr, ipos, deg, rowcnt, rowbase, edges_tmp, edges, min_accept, rdepth, pool, ctl;
     DevBuf pstat, ecnt;  // per-problem counters of multi-dataset searches
     DevBuf pair_part;    // partial Gram tiles of depth 0 through the pair contraction
+    DevBuf tri_node, tri_rowoff, tri_eidx, tri_part;  // depth 1 through the masked contractions
     DevBuf pairs_setup, pairs_out;  // bns_ci_pairs: tile plan and results
     DevBuf err_val, err_tag, err_cnt;  // verification log
     // bytes of the last search set-up uploaded into `setup` (a repeated
@@ -649,6 +652,9 @@ static const int64_t kPairPartMax = 1ll << 30;
 // MI355X, 8.9e7 (60 variables, 50,000 samples) is faster in the test kernel,
 // 2.4e9 (220 variables, 100,000 samples) and more through the contraction.
 static const double kPairsAutoWork = 5e8;
+// Depth 1 through the masked contractions: work items held at most (64 KiB
+// each; beyond, the depth runs in the test kernel).
+static const int64_t kTriItemsMax = 16384;
 
 static bns_status plan_pairs(const DevCtx &dc, const bns_dataset *const *ds, int32_t P, PairPlan &pp) {
     pp = PairPlan();
@@ -884,12 +890,15 @@ static const size_t kSpecPoolWords = 64u << 10;
 
 // Captures (once per distinct argument set) K consecutive depth sequences as
 // one executable graph; the depth index lives in the device control block, so
-// the same graph serves every starting depth.
-static bns_status depth_graph(DevCtx &dc, const DepthArgs &a, int grid, int K, bool init, hipStream_t s,
-                              GraphEntry **out) {
+// the same graph serves every starting depth.  Sequence tri_seq (if any) also
+// holds the depth-1 contraction kernels, which act only when the device's
+// depth is 1.
+static bns_status depth_graph(DevCtx &dc, const DepthArgs &a, int grid, int K, bool init, int tri_seq,
+                              hipStream_t s, GraphEntry **out) {
     for (size_t i = 0; i < dc.graphs.size(); ++i) {
         GraphEntry *g = dc.graphs[i].get();
-        if (g->K == K && g->grid == grid && g->init == init && std::memcmp(&g->args, &a, sizeof(a)) == 0) {
+        if (g->K == K && g->grid == grid && g->init == init && g->tri_seq == tri_seq &&
+            std::memcmp(&g->args, &a, sizeof(a)) == 0) {
             // most recently used last: eviction takes the front
             std::rotate(dc.graphs.begin() + i, dc.graphs.begin() + i + 1, dc.graphs.end());
             *out = g;
@@ -905,10 +914,12 @@ static bns_status depth_graph(DevCtx &dc, const DepthArgs &a, int grid, int K, b
     g->grid = grid;
     g->K = K;
     g->init = init;
+    g->tri_seq = tri_seq;
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t e = init ? launch_init_search(a, s) : hipSuccess;
     for (int i = 0; i < K && e == hipSuccess; ++i) {
         e = launch_depth_prepare(a, s);
+        if (e == hipSuccess && i == tri_seq) e = launch_depth1_gram(a, s);
         if (e == hipSuccess) e = (init && i == 0 && a.pairs.part) ? launch_depth0_pairs(a, s) : launch_depth_tests(a, grid, s);
         if (e == hipSuccess) e = launch_depth_apply(a, s);
     }
@@ -1001,6 +1012,42 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
         for (int32_t k = 0; k < P; ++k) work += 0.5 * (double)ds[k]->n * (ds[k]->n - 1) * (double)ds[k]->m;
         if (work >= kPairsAutoWork && plan_pairs(dc, ds, P, pp) != BNS_OK) pp = PairPlan();
     }
+    // Depth 1 through the masked Gram contractions (batched form; verification
+    // mode keeps the test kernel, as at depth 0).
+    bool tri_on = false;
+    int64_t tri_cap = 0;
+    int tri_target = 0, tri_grid = 0;
+    // The automatic choice is the test kernel: the contraction evaluates every
+    // depth-1 test, where the sequential order stops each edge at its first
+    // accepting one (3x to 10x fewer tests on the measured workloads), and
+    // each tile streams its variables' columns again (cfg4: 4.0 M tests and
+    // 103 GB of column reads against 0.38 M tests in the test kernel).
+    if (!verify && o.form == BNS_FORM_BATCHED && (unbounded || dmax >= 1) && o.depth1 == BNS_DEPTH1_GRAM) {
+        bool cards_ok = true;
+        for (int32_t k = 0; k < P; ++k)
+            for (uint8_t cv : ds[k]->cards) cards_ok = cards_ok && cv >= kTriMinCard && cv <= kTriMaxCard;
+        tri_on = cards_ok;
+        if (tri_on) {
+            const int occ = tri_max_wg_per_cu();
+            tri_target = 2 * dc.num_cu * occ;
+            tri_grid = dc.num_cu * occ;
+            // items if every node kept all its neighbours, plus room for the
+            // sample chunks of small plans
+            int64_t base_ub = 0;
+            for (int32_t k = 0; k < P; ++k) {
+                int64_t Rtot = 0;
+                for (uint8_t cv : ds[k]->cards) Rtot += cv;
+                for (uint8_t cv : ds[k]->cards) {
+                    const int64_t nb = (Rtot - cv + 63) / 64;
+                    base_ub += nb * (nb + 1) / 2 * ((cv + kTriCats - 1) / kTriCats);
+                }
+            }
+            tri_cap = std::min<int64_t>(kTriItemsMax, (int64_t)tri_target + 2 * base_ub);
+        }
+    }
+    const double tri_bytes = tri_on ? (double)sizeof(TriNode) * G + 8.0 * (double)adj_total +
+                                          (double)tri_cap * kTriCats * 64 * 64 * 4
+                                    : 0.0;
     const size_t o_gp = al8(o_cards + (size_t)G);
     const size_t o_ohvar = al8(o_gp + sizeof(GramProb) * pp.gps.size());
     const size_t o_ohcat = al8(o_ohvar + sizeof(int32_t) * pp.oh_var.size());
@@ -1016,7 +1063,7 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
                             16.0 * G + (2.0 * sizeof(EdgeRec) + 8.0) * (double)pairs_total + sizeof(Ctl) +
                             4.0 * (double)kSplitWords + 4.0 * (double)kSplitTickets +
                             4.0 * 1024 + (per_prob ? sizeof(PStatDev) * (double)P * kMaxDepths + 8.0 * pairs_total : 0.0) +
-                            8.0 * (double)err_cap + (double)(pp.part_bytes + pp.gram_bytes);
+                            8.0 * (double)err_cap + (double)(pp.part_bytes + pp.gram_bytes) + tri_bytes;
         st = check_workspace(o, need, "the skeleton search");
         if (st != BNS_OK) return st;
     }
@@ -1064,6 +1111,12 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     HIP_TRY(dc.pstat.ensure(per_prob ? sizeof(PStatDev) * (size_t)P * kMaxDepths : 256));
     HIP_TRY(dc.ecnt.ensure(per_prob ? sizeof(uint32_t) * 2 * (size_t)pairs_total : 256));
     if (pp.on) HIP_TRY(dc.pair_part.ensure((size_t)(pp.part_bytes + pp.gram_bytes)));
+    if (tri_on) {
+        HIP_TRY(dc.tri_node.ensure(sizeof(TriNode) * (size_t)G));
+        HIP_TRY(dc.tri_rowoff.ensure(sizeof(int32_t) * (size_t)adj_total));
+        HIP_TRY(dc.tri_eidx.ensure(sizeof(int32_t) * (size_t)adj_total));
+        HIP_TRY(dc.tri_part.ensure(sizeof(int32_t) * (size_t)tri_cap * kTriCats * 64 * 64));
+    }
     if (!dc.split_tab.p || dc.split_dirty) {
         HIP_TRY(dc.split_tab.ensure(sizeof(uint32_t) * (size_t)kSplitWords));
         HIP_TRY(dc.split_cnt.ensure(sizeof(uint32_t) * (size_t)kSplitTickets));
@@ -1138,6 +1191,15 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
         a.pairs.T = pp.T;
         a.pairs.n_gp = P;
         a.pairs.gram_grid = (int)std::min<int64_t>(pp.items, (int64_t)dc.num_cu * gram_max_wg_per_cu(pp.T));
+    }
+    if (tri_on) {
+        a.tri.node = dc.tri_node.as<TriNode>();
+        a.tri.rowoff = dc.tri_rowoff.as<int32_t>();
+        a.tri.eidx = dc.tri_eidx.as<int32_t>();
+        a.tri.part = dc.tri_part.as<int32_t>();
+        a.tri.part_items = tri_cap;
+        a.tri.target_items = tri_target;
+        a.tri.grid = tri_grid;
     }
 
     const int lds_bytes = tile.lds_words * 4;
@@ -1218,8 +1280,11 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
         a.pub_seq = (unsigned long long *)dc.pub;
         a.pub_cnt = (unsigned int *)((char *)dc.pub + 8);
         a.h_flag = dc.h_flag;
+        // the sequence of this launch that holds depth 1, when it runs
+        // through the contraction
+        const int tri_seq = (tri_on && d <= 1 && 1 < d + K) ? 1 - d : -1;
         if (use_graph) {
-            st = depth_graph(dc, a, grid, K, d == 0, s, &ge);
+            st = depth_graph(dc, a, grid, K, d == 0, tri_seq, s, &ge);
             if (st != BNS_OK) return st;
             HIP_TRY(hipGraphLaunch(ge->exec, s));
             HIP_TRY(hipEventRecord(ge->done, s));
@@ -1231,6 +1296,11 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
                     if (o.timing) HIP_TRY(hipEventRecord(evg.v[0], s));
                     HIP_TRY(launch_depth0_pairs(a, s));
                     if (o.timing) HIP_TRY(hipEventRecord(evg.v[1], s));
+                } else if (i == tri_seq) {
+                    if (o.timing) HIP_TRY(hipEventRecord(evg.v[2 * i], s));
+                    HIP_TRY(launch_depth1_gram(a, s));
+                    HIP_TRY(launch_depth_tests(a, grid, s));
+                    if (o.timing) HIP_TRY(hipEventRecord(evg.v[2 * i + 1], s));
                 } else if (o.timing) {
                     HIP_TRY(launch_depth_tests(a, grid, s, evg.v[2 * i], evg.v[2 * i + 1]));
                 } else {
@@ -1600,17 +1670,18 @@ static std::vector<TuneEntry> g_tune;
 static bool g_tune_loaded = false;
 
 // The tuned options that are kept (stream excluded), in file order.
+static const int kTuneFields = 11;
 static int32_t *tune_field(bns_options &o, int i) {
     int32_t *f[] = {&o.test_group, &o.max_replicas, &o.lds_bytes, &o.tickets_per_grab, &o.split_min_samples,
                     &o.units_per_group, &o.depth0, &o.round_tests, (int32_t *)&o.wave_depths,
-                    (int32_t *)&o.block_depths};
-    return i < 10 ? f[i] : nullptr;
+                    (int32_t *)&o.block_depths, &o.depth1};
+    return i < kTuneFields ? f[i] : nullptr;
 }
 
 // Persistent cache of tuned options: the file named by BNS_TUNE_CACHE, else
 // $XDG_CACHE_HOME/bns_autotune.txt, else $HOME/.cache/bns_autotune.txt (no
 // file when none is set).  One line per entry:
-//   bns2 <device> <key, comma-separated> <ten option values>
+//   bns3 <device> <key, comma-separated> <eleven option values>
 // Unreadable or malformed lines are ignored; the file is only a shortcut
 // (options never change results).
 static std::string tune_path() {
@@ -1629,7 +1700,7 @@ static void tune_load_file() {
     while (std::getline(f, line)) {
         std::istringstream in(line);
         std::string tag, dev, keys;
-        if (!(in >> tag >> dev >> keys) || tag != "bns2") continue;
+        if (!(in >> tag >> dev >> keys) || tag != "bns3") continue;
         TuneEntry e;
         e.device = dev;
         bool ok = true;
@@ -1640,7 +1711,7 @@ static void tune_load_file() {
             ok = !tok.empty() && *end == '\0';
         }
         bns_options_default(&e.best);
-        for (int i = 0; i < 10 && ok; ++i) {
+        for (int i = 0; i < kTuneFields && ok; ++i) {
             long long v = 0;
             if (!(in >> v)) ok = false;
             else *tune_field(e.best, i) = (int32_t)v;
@@ -1655,10 +1726,10 @@ static void tune_save_entry(const TuneEntry &e) {
     if (path.empty()) return;
     FILE *f = std::fopen(path.c_str(), "a");
     if (!f) return;  // a cache that cannot be written is not an error
-    std::fprintf(f, "bns2 %s ", e.device.c_str());
+    std::fprintf(f, "bns3 %s ", e.device.c_str());
     for (size_t i = 0; i < e.key.size(); ++i) std::fprintf(f, "%s%lld", i ? "," : "", (long long)e.key[i]);
     bns_options o = e.best;
-    for (int i = 0; i < 10; ++i) std::fprintf(f, " %d", *tune_field(o, i));
+    for (int i = 0; i < kTuneFields; ++i) std::fprintf(f, " %d", *tune_field(o, i));
     std::fprintf(f, "\n");
     std::fclose(f);
 }
@@ -1696,7 +1767,7 @@ extern "C" bns_status bns_autotune(const bns_dataset *const *ds, int32_t n_probl
         device = buf;
     }
     // options that base fixes are part of the key
-    for (int i = 0; i < 10; ++i) key.push_back(*tune_field(o, i));
+    for (int i = 0; i < kTuneFields; ++i) key.push_back(*tune_field(o, i));
     key.push_back(o.statistic);
     key.push_back(o.df_rule);
     {
@@ -1705,7 +1776,7 @@ extern "C" bns_status bns_autotune(const bns_dataset *const *ds, int32_t n_probl
         for (const TuneEntry &e : g_tune)
             if (e.device == device && e.key == key) {
                 *best = o;
-                for (int i = 0; i < 10; ++i) *tune_field(*best, i) = *tune_field(const_cast<bns_options &>(e.best), i);
+                for (int i = 0; i < kTuneFields; ++i) *tune_field(*best, i) = *tune_field(const_cast<bns_options &>(e.best), i);
                 best->stream = o.stream;
                 return BNS_OK;
             }
@@ -1834,6 +1905,18 @@ extern "C" bns_status bns_autotune(const bns_dataset *const *ds, int32_t n_probl
                     cur_t = t;
                 }
             }
+    }
+    // Depth 1 in the test kernel or through the masked contractions.
+    if (o.depth1 == BNS_DEPTH1_AUTO) {
+        bns_options c = cur;
+        c.depth1 = BNS_DEPTH1_GRAM;
+        double t = 0.0;
+        st = timed(c, &t);
+        if (st != BNS_OK && st != BNS_E_NOMEM) return st;
+        if (st == BNS_OK && t < cur_t * 0.98) {
+            cur = c;
+            cur_t = t;
+        }
     }
     // Depth 0 in the test kernel or through the pair contraction.
     if (o.depth0 == BNS_DEPTH0_AUTO) {

@@ -1,0 +1,42 @@
+// Shared pieces of the one-hot Gram contractions on gfx950 int8 MFMA (depth
+// 0 over all variables, depth 1 over each node's neighbours under a mask):
+// operand types, pipeline constants and the one-hot expansion of uint8
+// columns.
+#pragma once
+
+#include "device_ci.h"
+
+namespace bns {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kGramWG = 256;
+constexpr int kKS = 64;         // samples per pipeline step (two MFMA k-steps of 32)
+constexpr int kRow = kKS + 16;  // LDS bytes per one-hot column and step (padding spreads banks)
+
+// One-hot bytes [b == cat] of the 16 samples in w; bytes at and beyond
+// nvalid are zero.  Variables of at most 8 categories take one byte permute
+// per 4 samples (the sample bytes select from a pool whose byte cat is 1);
+// wider ones an exact zero-byte test of w ^ cat.
+BNS_INLINE u32x4 onehot16(u32x4 w, uint32_t plo, uint32_t phi, uint32_t cat, bool wide, int nvalid) {
+    u32x4 o;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t x = w[k];
+        uint32_t r;
+        if (!wide) {
+            r = __builtin_amdgcn_perm(phi, plo, x);
+        } else {
+            const uint32_t d = x ^ (cat * 0x01010101u);
+            const uint32_t t = ~(((d & 0x7f7f7f7fu) + 0x7f7f7f7fu) | d | 0x7f7f7f7fu);
+            r = t >> 7;
+        }
+        const int vk = nvalid - 4 * k;
+        const uint32_t keep = vk >= 4 ? 0xffffffffu : vk <= 0 ? 0u : ((1u << (8 * vk)) - 1u);
+        o[k] = r & keep;
+    }
+    return o;
+}
+
+}  // namespace bns

@@ -43,6 +43,42 @@ struct PairArgs {
     int32_t pad;
 };
 
+// Depth 1 as masked Gram contractions.  Every depth-1 test of an edge (x, y)
+// conditions on one z from the frozen neighbours of one endpoint, the owner u
+// of that side (x on side A, y on side B).  With H the one-hot columns of
+// u's neighbours and m_c the samples where X_u = c, the masked Gram matrix
+// G_c = H^T diag(m_c) H holds N[u = c][v = a][w = b] for every pair of
+// neighbours v, w of u: every depth-1 table of the tests u owns is a block of
+// G_0 .. G_{r_u - 1}, and the diagonals are the (u, v) marginals.  A work item
+// is one T x T tile (upper triangle of tile blocks) of up to four masks of one
+// node over one chunk of samples.
+constexpr int kTriCats = 4;      // masks (categories of the owner) per work item
+constexpr int kTriMinCard = 2;   // cardinality range of the path: at most T / 2 + 1 neighbours per
+constexpr int kTriMaxCard = 8;   // tile block, one-hot bytes by one byte permute
+
+struct TriNode {
+    int64_t item_base;   // first work item of the node
+    int64_t base_base;   // first (tile, category group) pair of the node
+    int64_t test_base;   // first depth-1 test owned by the node (deg (deg - 1) tests)
+    int32_t deg;         // frozen degree at depth 1 (0: no tests owned)
+    int32_t R;           // one-hot rows of the node's neighbours
+    int32_t nb;          // tile blocks per side
+    int32_t ncg;         // category groups of the node (of up to kTriCats)
+    int32_t nch;         // sample chunks
+    int32_t pad;
+};
+
+struct TriArgs {
+    TriNode *node;        // per global variable (null: depth 1 uses the test kernel)
+    int32_t *rowoff;      // per problem n*n block as nbr: rowoff[u n + k] = first one-hot row of the
+                          // k-th neighbour of u; entry deg holds R
+    int32_t *eidx;        // per problem n*n block: edge record of (u, k-th neighbour of u), or -1
+    int32_t *part;        // kTriCats T*T int32 per work item (chunk 0 holds the sums)
+    int64_t part_items;   // capacity of part in work items
+    int32_t target_items; // work items aimed for (sample chunks are cut toward it)
+    int32_t grid;         // workgroups of the contraction kernel
+};
+
 // Arguments of the per-depth pipeline of a skeleton search (all device pointers).
 struct DepthArgs {
     const ProbDev *probs;
@@ -115,6 +151,7 @@ struct DepthArgs {
     unsigned int *pub_cnt;        // device: workgroups of the current publish done (0 between)
     unsigned long long *h_flag;   // pinned host
     PairArgs pairs;               // depth 0 as one contraction (pairs.part non-null)
+    TriArgs tri;                  // depth 1 as masked contractions (tri.node non-null)
 };
 
 // Small searches keep the adjacency as bit rows in LDS and prepare each depth
@@ -138,6 +175,12 @@ hipError_t launch_ci_pairs(const PairArgs &p, const uint8_t *cards, int32_t n, d
                            int df_rule, double *stat_out, int64_t *df_out, double *p_out, int32_t *flags_out,
                            hipStream_t s);
 int gram_max_wg_per_cu(int T);
+// Depth 1 through the masked contractions: plan, tiles, chunk sums and one
+// decision per test (the depth's test kernel then returns at once).  Runs
+// only when the control block's depth is 1; falls back to the test kernel
+// when the plan exceeds the tile buffer.
+hipError_t launch_depth1_gram(const DepthArgs &a, hipStream_t s);
+int tri_max_wg_per_cu();
 int depth_tests_max_wg_per_cu(int lds_bytes);
 int depth_tests_fit_lds(int lds_per_cu);  // default dynamic LDS at full occupancy
 hipError_t allow_dynamic_lds(int bytes);  // raises the per-kernel dynamic LDS limit

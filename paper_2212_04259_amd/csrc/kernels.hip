@@ -129,6 +129,7 @@ __global__ void k_init_search(DepthArgs A) {
             c->total_tickets = 0;
             c->pool_used = 0;
             c->apply_done = 0;
+            c->gram_depth = -1;
         }
         for (int i = threadIdx.x; i < kMaxDepths; i += blockDim.x) {
             DepthStatDev z = {};
@@ -1058,7 +1059,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
     // set-up is loaded in one round: header, level table, binomial slice,
     // problem records and cardinalities.
     if (threadIdx.x == 0) {
-        hdr.quit = (c->done | c->error) != 0;
+        // (a depth whose tests ran through the Gram contraction: nothing to do)
+        hdr.quit = (c->done | c->error) != 0 || c->gram_depth == c->depth;
         hdr.d = c->depth;
         hdr.total = c->total_tickets;
         hdr.units = c->total_units;

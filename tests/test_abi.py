@@ -39,10 +39,10 @@ def test_options_defaults(bns):
     assert o.precision == bns.BNS_PREC_FP32_RECHECK
     assert o.recheck_band == 1e-3
     assert o.use_graph == 1 and o.timing == 0
-    assert o.wave_depths == 0 and o.block_depths == 0 and list(o.reserved) == [0, 0] and o.round_tests == 0
+    assert o.wave_depths == 0 and o.block_depths == 0 and o.reserved == 0 and o.round_tests == 0
     assert o.report_errors == 0 and o.workspace_mb == 0
     assert o.statistic == bns.BNS_STAT_G2 and o.df_rule == bns.BNS_DF_DECLARED
-    assert o.depth0 == bns.BNS_DEPTH0_AUTO
+    assert o.depth0 == bns.BNS_DEPTH0_AUTO and o.depth1 == bns.BNS_DEPTH1_AUTO
 
 
 @pytest.mark.parametrize("data,cards,alpha,maxd,msg", [
@@ -72,14 +72,14 @@ def test_bad_options_rejected(bns):
     with pytest.raises(bns.BnsError):
         bns.bns_pc_skeleton(np.zeros((3, 10), np.uint8), np.array([2, 2, 2], np.uint8), options=o)
     o = bns.bns_options_default()
-    o.reserved[1] = 1
+    o.reserved = 1
     with pytest.raises(bns.BnsError):
         bns.bns_pc_skeleton(np.zeros((3, 10), np.uint8), np.array([2, 2, 2], np.uint8), options=o)
     for bad in (dict(split_min_samples=-2), dict(units_per_group=-1), dict(units_per_group=5000),
                 dict(test_group=3), dict(test_group=-1), dict(max_replicas=3),
                 dict(max_replicas=128), dict(tickets_per_grab=9), dict(tickets_per_grab=-1),
                 dict(ticket_runs=3), dict(ticket_runs=-1),
-                dict(wave_depths=0b110, block_depths=0b011), dict(report_errors=2),
+                dict(wave_depths=0b110, block_depths=0b011), dict(report_errors=2), dict(depth1=3), dict(depth1=-1),
                 dict(report_errors=-1), dict(workspace_mb=-1), dict(statistic=2), dict(statistic=-1),
                 dict(df_rule=2), dict(depth0=3), dict(depth0=-1), dict(round_tests=-1),
                 dict(round_tests=65537), dict(form=3)):
