@@ -275,6 +275,8 @@ def main():
                     help="bit d set: one workgroup per test at depth d")
     ap.add_argument("--depth0", type=int, default=0, help="0 auto, 1 test kernel, 2 pair tables")
     ap.add_argument("--depth1", type=int, default=0, help="0 auto, 1 test kernel, 2 masked Gram tables")
+    ap.add_argument("--group-tests", type=int, default=0,
+                    help="depth 1 work units: 0 auto, 1 one test, 2 one edge's ranks of a level")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
@@ -325,7 +327,8 @@ def main():
                  split_min_samples=a.split_min, units_per_group=a.units_per_group,
                  test_group=a.test_group, max_replicas=a.max_replicas,
                  tickets_per_grab=a.tickets_per_grab, wave_depths=a.wave_depths,
-                 block_depths=a.block_depths, depth0=a.depth0, depth1=a.depth1)
+                 block_depths=a.block_depths, depth0=a.depth0, depth1=a.depth1,
+                 group_tests=a.group_tests)
     opt = bns.bns_options_default(**knobs)
     tuned = None
     if not a.no_autotune:
@@ -333,7 +336,8 @@ def main():
         opt = bns.bns_autotune(handles, alphas, maxd, opt)
         tuned = {f: getattr(opt, f) for f in ("test_group", "max_replicas", "lds_bytes",
                                                "tickets_per_grab", "wave_depths", "block_depths",
-                                               "split_min_samples", "units_per_group", "depth0", "depth1")}
+                                               "split_min_samples", "units_per_group", "depth0", "depth1",
+                                               "group_tests")}
         knobs.update(tuned)
 
     def step(o):

@@ -138,7 +138,8 @@ typedef struct bns_options {
                               accept was seen count as executed (speculative) tests */
     int32_t depth1;        /* batched form, depth 1 (conditioning sets of one variable):
                               BNS_DEPTH1_* (default automatic) */
-    int32_t reserved;      /* must be zero */
+    int32_t group_tests;   /* batched form, depth 1 in the test kernel: BNS_GROUP_* (default
+                              automatic) */
     void *stream;          /* hipStream_t; NULL = default stream */
 } bns_options;
 
@@ -183,6 +184,20 @@ enum {
                                results are those of Algorithm 1.  Needs cardinalities in [2, 8];
                                otherwise, in verification mode, in the edge-level form, or
                                when the plan exceeds the tile buffer, the test kernel runs */
+};
+
+/* Work units of depth 1 in the test kernel (the counterpart of Section IV-B's
+ * group of tests of one edge). */
+enum {
+    BNS_GROUP_AUTO = 0,   /* EDGE when some dataset's columns (variables x samples bytes)
+                             exceed 64 MiB, a quarter of MI355X's last-level cache (its tests
+                             would re-read X and Y from DRAM), else TEST */
+    BNS_GROUP_TEST = 1,   /* one test per work unit */
+    BNS_GROUP_EDGE = 2    /* one edge's ranks of a work-queue level per unit, counted in one
+                             pass over the samples that loads X and Y once and adds each
+                             test's table (up to 8 per pass; the unit stops after the pass
+                             with its first acceptance).  Doubling levels only (round_tests
+                             0); verification mode keeps one test per unit */
 };
 
 /* Fills *opt with the defaults.  opt must not be NULL. */
@@ -341,7 +356,8 @@ bns_status bns_pc_skeleton_batch(const bns_dataset *const *ds, int32_t n_problem
  *      (a grid of at most 27), then step 1 again under the chosen options;
  *   3. samples per work unit: split_min_samples in {default, 2048, 8192,
  *      16384, never} x units_per_group in {default, 4, 16};
- *   4. the depth-1 path (the test kernel or the masked contractions);
+ *   4. depth 1's work units (one test, or one edge's ranks of a level) and
+ *      its path (the test kernel or the masked contractions);
  *   5. the depth-0 path (the test kernel or the pair contraction).
  * A candidate is kept only if the whole search gets clearly faster.  *best
  * receives base with the chosen options filled in (base NULL = defaults).

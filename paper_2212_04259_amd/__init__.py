@@ -18,6 +18,9 @@ from ._lib import (  # noqa: F401
     BNS_DF_ADJUSTED,
     BNS_DF_DECLARED,
     BNS_FORM_BATCHED,
+    BNS_GROUP_AUTO,
+    BNS_GROUP_EDGE,
+    BNS_GROUP_TEST,
     BNS_FORM_EDGE,
     BNS_FORM_PLAIN,
     BNS_PREC_FP32_RECHECK,

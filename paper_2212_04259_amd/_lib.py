@@ -25,6 +25,7 @@ BNS_STAT_G2, BNS_STAT_X2 = 0, 1
 BNS_DF_DECLARED, BNS_DF_ADJUSTED = 0, 1
 BNS_DEPTH0_AUTO, BNS_DEPTH0_TESTS, BNS_DEPTH0_PAIRS = 0, 1, 2
 BNS_DEPTH1_AUTO, BNS_DEPTH1_TESTS, BNS_DEPTH1_GRAM = 0, 1, 2
+BNS_GROUP_AUTO, BNS_GROUP_TEST, BNS_GROUP_EDGE = 0, 1, 2
 STATUS_NAMES = {0: "BNS_OK", 1: "BNS_E_INVALID_ARG", 2: "BNS_E_VALUE_RANGE",
                 3: "BNS_E_TABLE_TOO_LARGE", 4: "BNS_E_NOMEM", 5: "BNS_E_DEVICE",
                 6: "BNS_E_INTERNAL"}
@@ -59,7 +60,7 @@ class bns_options(ctypes.Structure):
                 ("workspace_mb", ctypes.c_int32), ("statistic", ctypes.c_int32),
                 ("df_rule", ctypes.c_int32), ("depth0", ctypes.c_int32),
                 ("round_tests", ctypes.c_int32), ("depth1", ctypes.c_int32),
-                ("reserved", ctypes.c_int32),
+                ("group_tests", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
 
 

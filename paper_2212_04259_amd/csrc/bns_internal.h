@@ -24,7 +24,13 @@ constexpr int kGrabStride = 16;     // 64-bit words between two counters (one 12
 constexpr int kBinomLds = 512;      // binomial entries of a depth staged for the test kernel
 
 // Status codes written by kernels into the control block.
-enum DevError : int32_t { kDevOk = 0, kDevTableTooLarge = 1, kDevTooManyTests = 2, kDevDepthTooLarge = 3 };
+enum DevError : int32_t {
+    kDevOk = 0,
+    kDevTableTooLarge = 1,
+    kDevTooManyTests = 2,
+    kDevDepthTooLarge = 3,
+    kDevUnitMismatch = 4  // the test kernel instance does not match the depth's work units
+};
 
 // One dataset of a (possibly multi-dataset) skeleton search.
 struct ProbDev {
@@ -102,6 +108,8 @@ struct Ctl {
     // pairs, the longest chunk count of a node and the samples per chunk.
     int32_t gram_depth;
     int32_t tri_nch_max;
+    int32_t xy;                        // test kernel: units are (edge, level) groups sharing X and Y
+    int32_t pad1;
     unsigned long long tri_items;
     unsigned long long tri_base;
     unsigned long long tri_tests;

@@ -108,7 +108,8 @@ static bns_status read_options(const bns_options *in, bns_options *out) {
         return fail(BNS_E_INVALID_ARG, "options.round_tests must be in [0, 65536]");
     if (out->depth1 < BNS_DEPTH1_AUTO || out->depth1 > BNS_DEPTH1_GRAM)
         return fail(BNS_E_INVALID_ARG, "options.depth1 must be a BNS_DEPTH1_* value");
-    if (out->reserved != 0) return fail(BNS_E_INVALID_ARG, "options.reserved must be zero");
+    if (out->group_tests < BNS_GROUP_AUTO || out->group_tests > BNS_GROUP_EDGE)
+        return fail(BNS_E_INVALID_ARG, "options.group_tests must be a BNS_GROUP_* value");
     return BNS_OK;
 }
 
@@ -145,6 +146,7 @@ struct GraphEntry {
     int K = 0;
     bool init = false;  // begins with the search's initialisation
     int tri_seq = -1;   // depth sequence that runs depth 1 through the Gram contraction
+    int xy_seq = -1;    // depth sequence that runs depth 1 in (edge, level) units
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;  // recorded after each replay
@@ -868,6 +870,7 @@ static bns_status dev_error(int32_t e) {
         case kDevTableTooLarge: return fail(BNS_E_TABLE_TOO_LARGE, "a test's contingency table exceeds the supported size");
         case kDevTooManyTests: return fail(BNS_E_TABLE_TOO_LARGE, "an edge has more conditioning sets than supported");
         case kDevDepthTooLarge: return fail(BNS_E_TABLE_TOO_LARGE, "the search exceeds the supported depth");
+        case kDevUnitMismatch: return fail(BNS_E_INTERNAL, "test kernel instance and work units disagree");
         default: return fail(BNS_E_INTERNAL, "device error %d", e);
     }
 }
@@ -894,10 +897,10 @@ static const size_t kSpecPoolWords = 64u << 10;
 // holds the depth-1 contraction kernels, which act only when the device's
 // depth is 1.
 static bns_status depth_graph(DevCtx &dc, const DepthArgs &a, int grid, int K, bool init, int tri_seq,
-                              hipStream_t s, GraphEntry **out) {
+                              int xy_seq, hipStream_t s, GraphEntry **out) {
     for (size_t i = 0; i < dc.graphs.size(); ++i) {
         GraphEntry *g = dc.graphs[i].get();
-        if (g->K == K && g->grid == grid && g->init == init && g->tri_seq == tri_seq &&
+        if (g->K == K && g->grid == grid && g->init == init && g->tri_seq == tri_seq && g->xy_seq == xy_seq &&
             std::memcmp(&g->args, &a, sizeof(a)) == 0) {
             // most recently used last: eviction takes the front
             std::rotate(dc.graphs.begin() + i, dc.graphs.begin() + i + 1, dc.graphs.end());
@@ -915,12 +918,15 @@ static bns_status depth_graph(DevCtx &dc, const DepthArgs &a, int grid, int K, b
     g->K = K;
     g->init = init;
     g->tri_seq = tri_seq;
+    g->xy_seq = xy_seq;
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t e = init ? launch_init_search(a, s) : hipSuccess;
     for (int i = 0; i < K && e == hipSuccess; ++i) {
         e = launch_depth_prepare(a, s);
         if (e == hipSuccess && i == tri_seq) e = launch_depth1_gram(a, s);
-        if (e == hipSuccess) e = (init && i == 0 && a.pairs.part) ? launch_depth0_pairs(a, s) : launch_depth_tests(a, grid, s);
+        if (e == hipSuccess)
+            e = (init && i == 0 && a.pairs.part) ? launch_depth0_pairs(a, s)
+                                                  : launch_depth_tests(a, grid, s, nullptr, nullptr, i == xy_seq);
         if (e == hipSuccess) e = launch_depth_apply(a, s);
     }
     if (e == hipSuccess) e = launch_publish(a, s);
@@ -1171,6 +1177,17 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     a.block_depths = o.block_depths;
     a.round_width = o.round_tests;
     a.edge_form = o.form == BNS_FORM_EDGE ? 1 : 0;
+    // depth 1 in (edge, level) units: doubling levels, batched form, not in
+    // verification mode; automatic for datasets whose columns exceed a
+    // quarter of the last-level cache (their tests re-read X and Y from
+    // DRAM: 1,000 variables x 200,000 samples ran depth 1 in 14.7 instead of
+    // 23.1 ms); smaller ones keep one test per unit, whose rank-major order
+    // skips more speculative tests (60 x 50,000: 204 against 143 us)
+    double nm_max = 0.0;
+    for (int32_t k = 0; k < P; ++k) nm_max = std::max(nm_max, (double)ds[k]->n * (double)ds[k]->m);
+    const bool xy_want = o.group_tests == BNS_GROUP_EDGE || (o.group_tests == BNS_GROUP_AUTO && nm_max > kGrabRunBytes);
+    a.xy_policy = (xy_want && o.form == BNS_FORM_BATCHED && o.round_tests == 0 && !verify && (unbounded || dmax >= 1))
+                      ? 1 : 0;
     a.grab_fixed = o.tickets_per_grab;
     // Columns beyond a quarter of the last-level cache: deal the tickets to
     // the grab counters in runs of 64 (edges that share a column run on one
@@ -1283,8 +1300,9 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
         // the sequence of this launch that holds depth 1, when it runs
         // through the contraction
         const int tri_seq = (tri_on && d <= 1 && 1 < d + K) ? 1 - d : -1;
+        const int xy_seq = (a.xy_policy && d <= 1 && 1 < d + K) ? 1 - d : -1;
         if (use_graph) {
-            st = depth_graph(dc, a, grid, K, d == 0, tri_seq, s, &ge);
+            st = depth_graph(dc, a, grid, K, d == 0, tri_seq, xy_seq, s, &ge);
             if (st != BNS_OK) return st;
             HIP_TRY(hipGraphLaunch(ge->exec, s));
             HIP_TRY(hipEventRecord(ge->done, s));
@@ -1299,12 +1317,12 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
                 } else if (i == tri_seq) {
                     if (o.timing) HIP_TRY(hipEventRecord(evg.v[2 * i], s));
                     HIP_TRY(launch_depth1_gram(a, s));
-                    HIP_TRY(launch_depth_tests(a, grid, s));
+                    HIP_TRY(launch_depth_tests(a, grid, s, nullptr, nullptr, i == xy_seq));
                     if (o.timing) HIP_TRY(hipEventRecord(evg.v[2 * i + 1], s));
                 } else if (o.timing) {
-                    HIP_TRY(launch_depth_tests(a, grid, s, evg.v[2 * i], evg.v[2 * i + 1]));
+                    HIP_TRY(launch_depth_tests(a, grid, s, evg.v[2 * i], evg.v[2 * i + 1], i == xy_seq));
                 } else {
-                    HIP_TRY(launch_depth_tests(a, grid, s));
+                    HIP_TRY(launch_depth_tests(a, grid, s, nullptr, nullptr, i == xy_seq));
                 }
                 HIP_TRY(launch_depth_apply(a, s));
             }
@@ -1670,18 +1688,18 @@ static std::vector<TuneEntry> g_tune;
 static bool g_tune_loaded = false;
 
 // The tuned options that are kept (stream excluded), in file order.
-static const int kTuneFields = 11;
+static const int kTuneFields = 12;
 static int32_t *tune_field(bns_options &o, int i) {
     int32_t *f[] = {&o.test_group, &o.max_replicas, &o.lds_bytes, &o.tickets_per_grab, &o.split_min_samples,
                     &o.units_per_group, &o.depth0, &o.round_tests, (int32_t *)&o.wave_depths,
-                    (int32_t *)&o.block_depths, &o.depth1};
+                    (int32_t *)&o.block_depths, &o.depth1, &o.group_tests};
     return i < kTuneFields ? f[i] : nullptr;
 }
 
 // Persistent cache of tuned options: the file named by BNS_TUNE_CACHE, else
 // $XDG_CACHE_HOME/bns_autotune.txt, else $HOME/.cache/bns_autotune.txt (no
 // file when none is set).  One line per entry:
-//   bns3 <device> <key, comma-separated> <eleven option values>
+//   bns4 <device> <key, comma-separated> <twelve option values>
 // Unreadable or malformed lines are ignored; the file is only a shortcut
 // (options never change results).
 static std::string tune_path() {
@@ -1700,7 +1718,7 @@ static void tune_load_file() {
     while (std::getline(f, line)) {
         std::istringstream in(line);
         std::string tag, dev, keys;
-        if (!(in >> tag >> dev >> keys) || tag != "bns3") continue;
+        if (!(in >> tag >> dev >> keys) || tag != "bns4") continue;
         TuneEntry e;
         e.device = dev;
         bool ok = true;
@@ -1726,7 +1744,7 @@ static void tune_save_entry(const TuneEntry &e) {
     if (path.empty()) return;
     FILE *f = std::fopen(path.c_str(), "a");
     if (!f) return;  // a cache that cannot be written is not an error
-    std::fprintf(f, "bns3 %s ", e.device.c_str());
+    std::fprintf(f, "bns4 %s ", e.device.c_str());
     for (size_t i = 0; i < e.key.size(); ++i) std::fprintf(f, "%s%lld", i ? "," : "", (long long)e.key[i]);
     bns_options o = e.best;
     for (int i = 0; i < kTuneFields; ++i) std::fprintf(f, " %d", *tune_field(o, i));
@@ -1905,6 +1923,20 @@ extern "C" bns_status bns_autotune(const bns_dataset *const *ds, int32_t n_probl
                     cur_t = t;
                 }
             }
+    }
+    // Depth 1 in units of one test or of one edge's ranks of a level.
+    if (o.group_tests == BNS_GROUP_AUTO) {
+        for (int32_t gt : {BNS_GROUP_TEST, BNS_GROUP_EDGE}) {
+            bns_options c = cur;
+            c.group_tests = gt;
+            double t = 0.0;
+            st = timed(c, &t);
+            if (st != BNS_OK) return st;
+            if (t < cur_t * 0.98) {
+                cur = c;
+                cur_t = t;
+            }
+        }
     }
     // Depth 1 in the test kernel or through the masked contractions.
     if (o.depth1 == BNS_DEPTH1_AUTO) {

@@ -139,7 +139,9 @@ struct DepthArgs {
     int32_t round_width;      // ticket levels: 0 doubling (level L: ranks [2^L - 1, 2^(L+1) - 1)); g > 0
                               // rounds of g ranks (level L < 63: [L g, (L + 1) g); level 63: the rest)
     int32_t edge_form;        // 1: one group per edge runs its tests in order to the first accept
-    int32_t pad2[2];
+    int32_t xy_policy;        // depth 1: a work unit is one edge's ranks of a level, counted in one pass
+                              // sharing the X and Y columns (0 never, 1 always)
+    int32_t pad2;
     // Results of a launch, written into pinned host memory by its last kernel.
     Ctl *h_ctl;               // copy of the control block
     char *h_res;              // null, or removal depths (res_rbytes) then the first removal records
@@ -162,8 +164,10 @@ __host__ __device__ bool small_search(const DepthArgs &a);
 hipError_t launch_depth_prepare(const DepthArgs &a, hipStream_t s);   // snapshot .. scatter
 // With start/stop events the runtime records them with the kernel's own
 // dispatch (tight bracketing of short kernels).
+// xy: the instance for a depth of (edge, level) units (depth 1 with
+// a.xy_policy set).
 hipError_t launch_depth_tests(const DepthArgs &a, int grid, hipStream_t s,
-                              hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+                              hipEvent_t start = nullptr, hipEvent_t stop = nullptr, bool xy = false);
 hipError_t launch_depth_apply(const DepthArgs &a, hipStream_t s);     // removals + finalize
 hipError_t launch_init_search(const DepthArgs &a, hipStream_t s);     // complete graph, reset
 hipError_t launch_publish(const DepthArgs &a, hipStream_t s);         // results into pinned host memory

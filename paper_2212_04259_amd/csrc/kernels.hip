@@ -362,9 +362,13 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
     // of an edge)
     const unsigned long long cnt = start;
     const int g = A.round_width;
+    // Depth 1 in (edge, level) units: one unit per edge and level, its ranks
+    // counted together (doubling levels only; not in verification mode)
+    const bool xy = A.xy_policy == 1 && d == 1 && g == 0 && !A.edge_form && A.err_val == nullptr;
     unsigned long long width = 1ull << (lane < 62 ? lane : 62);
     if (g > 0) width = lane < 63 ? (unsigned long long)g
                                  : (maxn > 63ull * g ? maxn - 63ull * g : (unsigned long long)g);
+    if (xy) width = 1ull;
     int bad = 0;
     unsigned long long tk = 0;
     if (cnt) {
@@ -410,7 +414,7 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
         // With more tickets the merges cost more than the idle groups.
         unsigned long long C = 1, cap = 0;
         long long Lc = A.m_max;
-        if (A.split_min > 0 && total > 0 && total <= (unsigned long long)A.split_tickets) {
+        if (!xy && A.split_min > 0 && total > 0 && total <= (unsigned long long)A.split_tickets) {
             const unsigned long long want =
                 (unsigned long long)max(A.units_per_group, 1) * groups / total;
             const unsigned long long by_len = (unsigned long long)(A.m_max / A.split_min);
@@ -429,6 +433,7 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
             cap = 0;
         }
         c->mode = mode;
+        c->xy = xy ? 1 : 0;
         c->chunks = (int)C;
         c->chunk_len = Lc;
         c->split_cap = cap;
@@ -818,6 +823,7 @@ struct Desc {
     int32_t prob;
     int32_t valid;
     int32_t ncols;
+    uint32_t xyk;            // (edge, level) units: ranks r .. r + xyk - 1 of the edge
     uint16_t var[kMaxCols];  // variable ids (n <= 65535)
     uint8_t card[kMaxCols];
 };
@@ -881,6 +887,8 @@ BNS_INLINE void decode_ticket(const DepthArgs &A, const unsigned long long *lvl_
     const unsigned long long ma =
         __hip_atomic_load(&A.min_accept[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     q.valid = (r < rec.n && (!skip_ok || r <= ma)) ? 1 : 0;
+    // (edge, level) units (width-1 levels of doubling ranks): the level's ranks
+    q.xyk = (uint32_t)min(1ull << (L < 62 ? L : 62), r < rec.n ? rec.n - r : 0ull);
     if (!q.valid) return;
     decode_edge_rank(A, e, r, rec, d, btab, bstride, brows, probs_lds, cards_lds, q);
 }
@@ -972,6 +980,277 @@ BNS_INLINE uint64_t table_cells(const TestSh &t) {
     return T;
 }
 
+// ---------------------------------------------------------------------------
+// Depth 1 in (edge, level) units: the ranks of one level of one edge differ
+// only in Z, so they are counted in one pass over the samples that loads the X
+// and Y columns once (Section IV-B groups the tests of an edge for the same
+// reason) and adds every test's own table; the tables' epilogues (replica
+// sums, marginals, statistic) run one table per wave, and the chi-square
+// tails one test per lane.  A pass holds up to kXY tests; a unit with more
+// runs in several passes and stops after the pass with the first acceptance.
+// ---------------------------------------------------------------------------
+constexpr int kXY = 8;
+
+// Descriptor of a pass, at the start of the group's LDS region.
+struct XYHdr {
+    const uint8_t *zcol[kXY];
+    double g2[kXY];
+    double df[kXY];
+    uint32_t rz[kXY];
+    uint32_t toff[kXY];   // word offset of test t's replicated counts after the header
+    uint32_t roff[kXY];   // word offset of its summed table (= toff when not replicated)
+    uint32_t moff[kXY];   // word offset of its marginals: rows, columns, strata
+    int32_t flag[kXY];    // FP64 re-check requests
+    int32_t first;        // first accepting test of the pass (kXY: none)
+    int32_t pad;
+};
+constexpr uint32_t kXYHdrWords = (uint32_t)((sizeof(XYHdr) + 15) / 16 * 4);
+
+struct XYOut {
+    int32_t first_accept;  // offset in the unit of its first accepting test, -1: none
+    uint32_t exec, rechecks;
+    int32_t err;
+};
+
+// Density of the chi-square tail's gamma variate at x = g2 / 2 (slope of the
+// tail in x), per lane.
+BNS_INLINE double chi2_dens_lane(double df, double g2) {
+    const double x = 0.5 * g2, a = 0.5 * df;
+    if (!(x > 0.0) || !(a > 0.0)) return 0.0;
+    return exp((a - 1.0) * log(x) - x - lgamma(a));
+}
+
+// Counts kb tables of one pass: table t at byte offset b_t (+4 replica)
+// counts cell x + rx y + rx ry z_t; two samples per register (as count_packed).
+BNS_INLINE void count_xy(const uint8_t *xc, const uint8_t *yc, const XYHdr &h, uint32_t tab_lo, int kb,
+                         uint32_t rx, uint32_t rxy, int logR, int64_t m, int rank, int S) {
+    const uint32_t rep = (uint32_t)rank & ((1u << logR) - 1u);
+    const uint32_t mx4 = __builtin_amdgcn_readfirstlane(1u << (logR + 2));
+    const uint32_t my4 = __builtin_amdgcn_readfirstlane(rx << (logR + 2));
+    const uint32_t mz4 = __builtin_amdgcn_readfirstlane(rxy << (logR + 2));
+    // per test: its table's byte offset (scalar) and Z column (scalar)
+    uint32_t bt[kXY];
+    const gvec4 *cz[kXY];
+#pragma unroll
+    for (int t = 0; t < kXY; ++t) {
+        bt[t] = __builtin_amdgcn_readfirstlane(tab_lo + 4u * h.toff[t < kb ? t : 0]);
+        cz[t] = uniform_col(h.zcol[t < kb ? t : 0]);
+    }
+    const uint32_t rep4 = 4u * rep, rep2 = rep4 | (rep4 << 16);
+    const gvec4 *cx = uniform_col(xc), *cy = uniform_col(yc);
+    const uint32_t nvec = (uint32_t)(m >> 4);
+    for (uint32_t i = (uint32_t)rank; i < nvec; i += (uint32_t)S) {
+        const u32x4 vx = cx[i], vy = cy[i];
+        u32x4 vz[kXY];
+#pragma unroll
+        for (int t = 0; t < kXY; ++t)
+            if (t < kb) vz[t] = cz[t][i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t bl = mad24(__builtin_amdgcn_perm(0u, vx[j], 0x0c020c00u), mx4,
+                                      mad24(__builtin_amdgcn_perm(0u, vy[j], 0x0c020c00u), my4, 0u));
+            const uint32_t bh = mad24(__builtin_amdgcn_perm(0u, vx[j], 0x0c030c01u), mx4,
+                                      mad24(__builtin_amdgcn_perm(0u, vy[j], 0x0c030c01u), my4, 0u));
+#pragma unroll
+            for (int t = 0; t < kXY; ++t) {
+                if (t >= kb) break;  // uniform
+                const uint32_t b2 = (bt[t] | (bt[t] << 16)) + rep2;
+                const uint32_t al = mad24(__builtin_amdgcn_perm(0u, vz[t][j], 0x0c020c00u), mz4, bl + b2);
+                const uint32_t ah = mad24(__builtin_amdgcn_perm(0u, vz[t][j], 0x0c030c01u), mz4, bh + b2);
+                lds_inc(al & 0xffffu);
+                lds_inc(al >> 16);
+                lds_inc(ah & 0xffffu);
+                lds_inc(ah >> 16);
+            }
+        }
+    }
+    // the last m mod 16 samples, one per lane
+    const int64_t s = ((int64_t)nvec << 4) + rank;
+    if (s < m) {
+        const uint32_t bxy = ((uint32_t)xc[s] + rx * (uint32_t)yc[s]) << (logR + 2);
+#pragma unroll
+        for (int t = 0; t < kXY; ++t) {
+            if (t >= kb) break;
+            const uint8_t *zcol = (const uint8_t *)cz[t];
+            lds_inc(bt[t] + rep4 + bxy + ((rxy * (uint32_t)zcol[s]) << (logR + 2)));
+        }
+    }
+}
+
+// Ranks q.r .. q.r + q.xyk - 1 of edge q.e at depth 1 (all lanes of the group).
+template <bool kGeneral>
+BNS_INLINE XYOut run_xy_unit(const Grp &g, TestSh &t, uint32_t *region, uint32_t W, const Tile &tile,
+                             const DepthArgs &A, const Desc &q) {
+    (void)t;
+    XYOut o{-1, 0u, 0u, kDevOk};
+    // the header at an 8-byte boundary, the tables after it
+    uint32_t *hreg = region + ((lds_offset(region) >> 2) & 1u);
+    XYHdr &h = *(XYHdr *)hreg;
+    uint32_t *tabs = hreg + kXYHdrWords;
+    const uint32_t Wt = W > kXYHdrWords + 1u ? W - kXYHdrWords - 1u : 0u;
+    const uint32_t rx = uni((uint32_t)q.card[0]), ry = uni((uint32_t)q.card[1]), rxy = rx * ry;
+    const int64_t m = uni(q.m);
+    const int64_t e = uni(q.e);
+    const unsigned long long r0 = uni(q.r);
+    const uint32_t k = uni(q.xyk);
+    const EdgeRec rec = A.edges[e];
+    const ProbDev P = A.probs[uni(q.prob)];
+    const int stat = kGeneral ? tile.stat : 0;
+    const bool adj = kGeneral && tile.df_rule != 0;
+    const bool fp64 = tile.fp64 != 0;
+    const double alpha = uni(q.alpha);
+    const uint8_t *xc = uni(q.data + (int64_t)q.var[0] * q.ld);
+    const uint8_t *yc = uni(q.data + (int64_t)q.var[1] * q.ld);
+    const uint32_t tab_lo = lds_offset(tabs);
+    const int nw = g.block ? kWaves : 1;
+    const int wv = g.block ? (int)(threadIdx.x >> 6) : 0;
+    const int lane = (int)(threadIdx.x & 63);
+    const Grp wg = Grp::wave();
+    uint32_t b0 = 0;
+    while (b0 < k) {
+        if (b0 > 0) {
+            // a lower rank of the edge has accepted: the rest are not needed
+            const unsigned long long ma = uni(
+                __hip_atomic_load(&A.min_accept[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            if (ma < r0 + b0) break;
+        }
+        const uint32_t kmax = min((uint32_t)kXY, k - b0);
+        // the pass's conditioning variables: rank r0 + b0 + i (lanes i)
+        if (g.rank < (int)kmax) {
+            const unsigned long long r = r0 + b0 + (unsigned long long)g.rank;
+            const bool sideA = r < rec.nA;
+            const int owner = sideA ? rec.i : rec.j;
+            const int skip = sideA ? rec.posj : rec.posi;
+            const int pos = (int)(sideA ? r : r - rec.nA);
+            const int z = A.nbr[P.adj_off + (int64_t)owner * P.n + pos + (pos >= skip ? 1 : 0)];
+            h.zcol[g.rank] = P.data + (int64_t)z * P.ld;
+            h.rz[g.rank] = A.cards[P.var_off + z];
+        }
+        g.sync();
+        // plan: the most tests (and then the most replication) whose tables
+        // fit the region with 16-bit byte addresses
+        uint32_t rz[kXY];
+#pragma unroll
+        for (int i = 0; i < kXY; ++i) rz[i] = i < (int)kmax ? uni(h.rz[i]) : 0u;
+        int kb = (int)kmax, logR = tile.max_rep_log2;
+        for (;;) {
+            uint32_t rep_w = 0, red_w = 0, mar_w = 0, cmax = 0;
+#pragma unroll
+            for (int i = 0; i < kXY; ++i)
+                if (i < kb) {
+                    rep_w += (rxy * rz[i]) << logR;
+                    red_w += logR > 0 ? rxy * rz[i] : 0u;
+                    mar_w += (rx + ry + 1u) * rz[i];
+                    cmax = max(cmax, rxy * rz[i]);
+                }
+            const bool fits = rep_w + red_w + mar_w <= Wt && tab_lo + 4u * rep_w <= 65536u;
+            const bool cheap = logR == 0 || ((int64_t)(cmax << logR) * 4 <= m + 16 * g.size);
+            if (fits && cheap) break;
+            if (logR > 0) --logR;
+            else if (--kb == 0) break;
+        }
+        if (kb == 0) {
+            o.err = kDevTableTooLarge;
+            return o;
+        }
+        // layout: replicated tables, then per test its summed table (when
+        // replicated) and its marginals
+        if (g.rank == 0) {
+            uint32_t off = 0;
+            for (int i = 0; i < kb; ++i) {
+                h.toff[i] = off;
+                off += (rxy * rz[i]) << logR;
+            }
+            for (int i = 0; i < kb; ++i) {
+                h.roff[i] = h.toff[i];
+                if (logR > 0) {
+                    h.roff[i] = off;
+                    off += rxy * rz[i];
+                }
+                h.moff[i] = off;
+                off += (rx + ry + 1u) * rz[i];
+            }
+            h.first = kXY;
+        }
+        uint32_t rep_words = 0;
+#pragma unroll
+        for (int i = 0; i < kXY; ++i)
+            if (i < kb) rep_words += (rxy * rz[i]) << logR;
+        g.sync();
+        for (uint32_t i = (uint32_t)g.rank; i < rep_words; i += (uint32_t)g.size) tabs[i] = 0u;
+        g.sync();
+        count_xy(xc, yc, h, tab_lo, kb, rx, rxy, logR, m, g.rank, g.size);
+        g.sync();
+        // per test: replica sums, marginals, statistic, df (one wave per test)
+        for (int i = wv; i < kb; i += nw) {
+            const uint32_t Tc = rxy * rz[i];
+            const uint32_t *rep_t = tabs + h.toff[i];
+            uint32_t *red = tabs + h.roff[i];
+            if (logR > 0) {
+                reduce_replicas(rep_t, red, Tc, logR, lane, 64);
+                wg.sync();
+            }
+            uint32_t *rows = tabs + h.moff[i], *cols = rows + rx * rz[i], *strata = cols + ry * rz[i];
+            marginals(wg, red, rows, cols, strata, rx, ry, rz[i]);
+            double st;
+            if (fp64) st = wave_sum(stat_partial<double>(wg, red, rows, cols, strata, rx, ry, rz[i], stat));
+            else st = (double)wave_sum(stat_partial<float>(wg, red, rows, cols, strata, rx, ry, rz[i], stat));
+            const double dfv = adj ? wave_sum(adj_df_partial(wg, rows, cols, strata, rx, ry, rz[i]))
+                                   : (double)(rx - 1) * (double)(ry - 1) * (double)rz[i];
+            if (lane == 0) {
+                h.g2[i] = stat ? st : 2.0 * st;
+                h.df[i] = dfv;
+            }
+        }
+        g.sync();
+        // tails (lane i of the group), FP64 re-checks near alpha
+        bool acc = false;
+        int flag = 0;
+        if (g.rank < kb) {
+            const double x = h.g2[g.rank], df = h.df[g.rank];
+            const double p = chi2_tail_lane((int64_t)df, x);
+            if (!fp64 && df > 0.0) {
+                const double gap = fabs(p - alpha);
+                const double rel = (32.0 + (double)(rxy * rz[g.rank]) / 64.0 + 1.0) * 5.96e-8 + 1e-6;
+                const double dp = chi2_dens_lane(df, x) * 0.5 * x * rel;
+                if (gap < tile.band || gap < 4.0 * dp) flag = 1;
+            }
+            h.flag[g.rank] = flag;
+            acc = !flag && p > alpha;
+        }
+        g.sync();
+        int nflag = 0;
+#pragma unroll
+        for (int i = 0; i < kXY; ++i)
+            if (i < kb) nflag += h.flag[i];
+        nflag = uni(nflag);
+        if (nflag > 0) {
+            for (int i = wv; i < kb; i += nw) {
+                if (!h.flag[i]) continue;
+                const uint32_t *red = tabs + h.roff[i];
+                const uint32_t *rows = tabs + h.moff[i], *cols = rows + rx * rz[i], *strata = cols + ry * rz[i];
+                const double st = wave_sum(stat_partial<double>(wg, red, rows, cols, strata, rx, ry, rz[i], stat));
+                if (lane == 0) h.g2[i] = stat ? st : 2.0 * st;
+            }
+            g.sync();
+            if (g.rank < kb && h.flag[g.rank])
+                acc = chi2_tail_lane((int64_t)h.df[g.rank], h.g2[g.rank]) > alpha;
+        }
+        if (acc) atomicMin(&h.first, g.rank);
+        g.sync();
+        const int first = h.first;
+        o.exec += (uint32_t)kb;
+        o.rechecks += (uint32_t)nflag;
+        g.sync();  // the header is rewritten by the next pass
+        if (first < kXY) {
+            o.first_accept = (int32_t)b0 + first;
+            break;
+        }
+        b0 += (uint32_t)kb;
+    }
+    return o;
+}
+
 static_assert(kGrabParts <= 8, "counter indices are packed into 3 bits");
 constexpr int kGrabPartsLog2 = 3;
 static_assert(kGrabParts == 1 << kGrabPartsLog2, "a power of two");
@@ -1021,7 +1300,7 @@ BNS_INLINE void group_bcast2_u64(const Grp &g, unsigned long long &a, unsigned l
 struct TestHdr {
     unsigned long long total, units, cap;
     long long Lc;
-    int32_t quit, d, C, mode, B, bstride, brows, pad;
+    int32_t quit, d, C, mode, B, bstride, brows, xy;
 };
 
 // Units of a grab: i0 + r (part < 0: the first, static batch) or
@@ -1038,7 +1317,9 @@ struct Batch {
 // its FP32 error logged); the timed searches use the other.
 // GENERAL: the instance for other statistics or df rules than G^2 with the
 // declared df.
-template <int LGB, bool VERIFY, bool GENERAL>
+// XY: the instance for a depth of (edge, level) units (run_xy_unit); a
+// separate instance keeps that path's registers out of the per-test one.
+template <int LGB, bool VERIFY, bool GENERAL, bool XY = false>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k_depth_tests(DepthArgs A) {
     extern __shared__ uint32_t lds[];
     __shared__ TestSh tsh[kWaves];
@@ -1071,6 +1352,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
         hdr.B = c->batch;
         hdr.bstride = c->bstride;
         hdr.brows = c->brows;
+        hdr.xy = c->xy;
     }
     if (threadIdx.x < kWaves) {
         tal_exec[threadIdx.x] = 0;
@@ -1101,6 +1383,10 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
     const long long Lc = uni(hdr.Lc);
     const uint64_t cap = uni(hdr.cap);
     const int mode = uni(hdr.mode);
+    if ((uni(hdr.xy) != 0) != XY) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) c->error = kDevUnitMismatch;
+        return;
+    }
     const int B0 = min(max(uni(hdr.B), 1), kSlotsPerWave);
     // binomials C(n, k), n <= max degree, k <= d: from the staged slice when
     // it fits, else from the full table
@@ -1163,6 +1449,26 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
         for (int j = 0; j < cnt; ++j) {
             const Desc &q = mine[j];
             if (!uni(q.valid)) continue;
+            if constexpr (XY) {
+                const XYOut xo = run_xy_unit<GENERAL>(g, t, region, W, A.tile, A, q);
+                if (g.rank == 0) {
+                    tal_exec[ti] += xo.exec;
+                    tal_re[ti] += xo.rechecks;
+                    tal_bytes[ti] += 3.0 * (double)xo.exec * (double)q.m;
+                    if (xo.err) c->error = xo.err;
+                    if (xo.first_accept >= 0)
+                        atomicMin(&A.min_accept[q.e], q.r + (unsigned long long)xo.first_accept);
+                    if (A.per_prob && xo.exec) {
+                        __hip_atomic_fetch_add(&A.ecnt[2 * (uint64_t)q.e], xo.exec, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                        if (xo.rechecks)
+                            __hip_atomic_fetch_add(&A.ecnt[2 * (uint64_t)q.e + 1], xo.rechecks, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+                g.sync();
+                continue;
+            }
             // Lane 0 fetches the next test's current first-accept rank while
             // this test runs and drops that test before it starts if a lower
             // rank of its edge has accepted meanwhile (the check at decode is
@@ -1726,8 +2032,12 @@ hipError_t launch_depth_prepare(const DepthArgs &a, hipStream_t s) {
 
 // Instance for the search: tickets dealt in runs when its columns exceed the
 // last-level cache's share (grab_block_log2 = kGrabRunLog2), else singly.
-static auto depth_tests_kernel(const DepthArgs &a) -> decltype(&k_depth_tests<0, false, false>) {
+static auto depth_tests_kernel(const DepthArgs &a, bool xy) -> decltype(&k_depth_tests<0, false, false>) {
     const bool general = a.tile.stat != 0 || a.tile.df_rule != 0;
+    if (xy) {
+        if (general) return &k_depth_tests<0, false, true, true>;
+        return a.grab_block_log2 ? &k_depth_tests<kGrabRunLog2, false, false, true> : &k_depth_tests<0, false, false, true>;
+    }
     // verification and other statistics: single-ticket dealing (the dealing
     // never changes results)
     if (a.err_val) return general ? &k_depth_tests<0, true, true> : &k_depth_tests<0, true, false>;
@@ -1736,8 +2046,8 @@ static auto depth_tests_kernel(const DepthArgs &a) -> decltype(&k_depth_tests<0,
 }
 
 hipError_t launch_depth_tests(const DepthArgs &a, int grid, hipStream_t s, hipEvent_t start,
-                              hipEvent_t stop) {
-    auto kern = depth_tests_kernel(a);
+                              hipEvent_t stop, bool xy) {
+    auto kern = depth_tests_kernel(a, xy);
     if (a.edge_form) kern = (a.tile.stat != 0 || a.tile.df_rule != 0) ? &k_depth_edges<true> : &k_depth_edges<false>;
     if (start && stop)
         hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kWG), (size_t)a.tile.lds_words * 4u, s, start, stop, 0, a);
@@ -1756,6 +2066,9 @@ hipError_t allow_dynamic_lds(int bytes) {
     const void *fns[] = {(const void *)k_depth_tests<kGrabRunLog2, false, false>,
                          (const void *)k_depth_tests<0, false, false>, (const void *)k_depth_tests<0, true, false>,
                          (const void *)k_depth_tests<0, false, true>, (const void *)k_depth_tests<0, true, true>,
+                         (const void *)k_depth_tests<0, false, false, true>,
+                         (const void *)k_depth_tests<kGrabRunLog2, false, false, true>,
+                         (const void *)k_depth_tests<0, false, true, true>,
                          (const void *)k_depth_edges<false>, (const void *)k_depth_edges<true>};
     hipError_t e = hipSuccess;
     for (const void *f : fns)

@@ -39,7 +39,7 @@ def test_options_defaults(bns):
     assert o.precision == bns.BNS_PREC_FP32_RECHECK
     assert o.recheck_band == 1e-3
     assert o.use_graph == 1 and o.timing == 0
-    assert o.wave_depths == 0 and o.block_depths == 0 and o.reserved == 0 and o.round_tests == 0
+    assert o.wave_depths == 0 and o.block_depths == 0 and o.group_tests == 0 and o.round_tests == 0
     assert o.report_errors == 0 and o.workspace_mb == 0
     assert o.statistic == bns.BNS_STAT_G2 and o.df_rule == bns.BNS_DF_DECLARED
     assert o.depth0 == bns.BNS_DEPTH0_AUTO and o.depth1 == bns.BNS_DEPTH1_AUTO
@@ -72,7 +72,7 @@ def test_bad_options_rejected(bns):
     with pytest.raises(bns.BnsError):
         bns.bns_pc_skeleton(np.zeros((3, 10), np.uint8), np.array([2, 2, 2], np.uint8), options=o)
     o = bns.bns_options_default()
-    o.reserved = 1
+    o.group_tests = 3
     with pytest.raises(bns.BnsError):
         bns.bns_pc_skeleton(np.zeros((3, 10), np.uint8), np.array([2, 2, 2], np.uint8), options=o)
     for bad in (dict(split_min_samples=-2), dict(units_per_group=-1), dict(units_per_group=5000),

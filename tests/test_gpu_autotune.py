@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 FIELDS = ("test_group", "max_replicas", "lds_bytes", "tickets_per_grab", "wave_depths",
-          "block_depths", "split_min_samples", "units_per_group", "depth0", "round_tests", "depth1")
+          "block_depths", "split_min_samples", "units_per_group", "depth0", "round_tests", "depth1", "group_tests")
 
 CHILD = r"""
 import json, sys, time
@@ -50,9 +50,9 @@ def _child(cache):
 
 def test_cache_file_is_shared_between_processes(tmp_path):
     cache = tmp_path / "tune.txt"
-    cache.write_text("not a tuning line\nbns3 gfx950/256cu 1,2,3 4 5\nbns3\n")
+    cache.write_text("not a tuning line\nbns4 gfx950/256cu 1,2,3 4 5\nbns4\n")
     first = _child(cache)
-    lines = [x for x in cache.read_text().splitlines() if x.startswith("bns3 gfx950")]
+    lines = [x for x in cache.read_text().splitlines() if x.startswith("bns4 gfx950")]
     assert len(lines) == 2, cache.read_text()  # the malformed one and the new entry
     assert first["split_min_samples"] in (0, 2048, 8192, 16384, -1)
     assert first["units_per_group"] in (0, 4, 16)
