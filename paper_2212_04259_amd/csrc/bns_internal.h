@@ -108,7 +108,7 @@ struct Ctl {
     // pairs, the longest chunk count of a node and the samples per chunk.
     int32_t gram_depth;
     int32_t tri_nch_max;
-    int32_t xy;                        // test kernel: units are (edge, level) groups sharing X and Y
+    int32_t xy;                        // test kernel units: 0 tests, 1 (edge, level) groups
     int32_t pad1;
     unsigned long long tri_items;
     unsigned long long tri_base;

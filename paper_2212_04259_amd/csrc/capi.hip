@@ -146,7 +146,7 @@ struct GraphEntry {
     int K = 0;
     bool init = false;  // begins with the search's initialisation
     int tri_seq = -1;   // depth sequence that runs depth 1 through the Gram contraction
-    int xy_seq = -1;    // depth sequence that runs depth 1 in (edge, level) units
+    uint32_t seq_units = 0;  // work units of each depth sequence's test kernel (2 bits each)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;  // recorded after each replay
@@ -897,10 +897,10 @@ static const size_t kSpecPoolWords = 64u << 10;
 // holds the depth-1 contraction kernels, which act only when the device's
 // depth is 1.
 static bns_status depth_graph(DevCtx &dc, const DepthArgs &a, int grid, int K, bool init, int tri_seq,
-                              int xy_seq, hipStream_t s, GraphEntry **out) {
+                              uint32_t seq_units, hipStream_t s, GraphEntry **out) {
     for (size_t i = 0; i < dc.graphs.size(); ++i) {
         GraphEntry *g = dc.graphs[i].get();
-        if (g->K == K && g->grid == grid && g->init == init && g->tri_seq == tri_seq && g->xy_seq == xy_seq &&
+        if (g->K == K && g->grid == grid && g->init == init && g->tri_seq == tri_seq && g->seq_units == seq_units &&
             std::memcmp(&g->args, &a, sizeof(a)) == 0) {
             // most recently used last: eviction takes the front
             std::rotate(dc.graphs.begin() + i, dc.graphs.begin() + i + 1, dc.graphs.end());
@@ -918,7 +918,7 @@ static bns_status depth_graph(DevCtx &dc, const DepthArgs &a, int grid, int K, b
     g->K = K;
     g->init = init;
     g->tri_seq = tri_seq;
-    g->xy_seq = xy_seq;
+    g->seq_units = seq_units;
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t e = init ? launch_init_search(a, s) : hipSuccess;
     for (int i = 0; i < K && e == hipSuccess; ++i) {
@@ -926,7 +926,8 @@ static bns_status depth_graph(DevCtx &dc, const DepthArgs &a, int grid, int K, b
         if (e == hipSuccess && i == tri_seq) e = launch_depth1_gram(a, s);
         if (e == hipSuccess)
             e = (init && i == 0 && a.pairs.part) ? launch_depth0_pairs(a, s)
-                                                  : launch_depth_tests(a, grid, s, nullptr, nullptr, i == xy_seq);
+                                                  : launch_depth_tests(a, grid, s, nullptr, nullptr,
+                                                                       (int)((seq_units >> (2 * i)) & 3u));
         if (e == hipSuccess) e = launch_depth_apply(a, s);
     }
     if (e == hipSuccess) e = launch_publish(a, s);
@@ -1300,9 +1301,11 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
         // the sequence of this launch that holds depth 1, when it runs
         // through the contraction
         const int tri_seq = (tri_on && d <= 1 && 1 < d + K) ? 1 - d : -1;
-        const int xy_seq = (a.xy_policy && d <= 1 && 1 < d + K) ? 1 - d : -1;
+        // the test kernel instance of each sequence (its depth's work units)
+        uint32_t seq_units = 0;
+        for (int i = 0; i < K; ++i) seq_units |= (uint32_t)depth_units(a, d + i) << (2 * i);
         if (use_graph) {
-            st = depth_graph(dc, a, grid, K, d == 0, tri_seq, xy_seq, s, &ge);
+            st = depth_graph(dc, a, grid, K, d == 0, tri_seq, seq_units, s, &ge);
             if (st != BNS_OK) return st;
             HIP_TRY(hipGraphLaunch(ge->exec, s));
             HIP_TRY(hipEventRecord(ge->done, s));
@@ -1317,12 +1320,12 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
                 } else if (i == tri_seq) {
                     if (o.timing) HIP_TRY(hipEventRecord(evg.v[2 * i], s));
                     HIP_TRY(launch_depth1_gram(a, s));
-                    HIP_TRY(launch_depth_tests(a, grid, s, nullptr, nullptr, i == xy_seq));
+                    HIP_TRY(launch_depth_tests(a, grid, s, nullptr, nullptr, depth_units(a, d + i)));
                     if (o.timing) HIP_TRY(hipEventRecord(evg.v[2 * i + 1], s));
                 } else if (o.timing) {
-                    HIP_TRY(launch_depth_tests(a, grid, s, evg.v[2 * i], evg.v[2 * i + 1], i == xy_seq));
+                    HIP_TRY(launch_depth_tests(a, grid, s, evg.v[2 * i], evg.v[2 * i + 1], depth_units(a, d + i)));
                 } else {
-                    HIP_TRY(launch_depth_tests(a, grid, s, nullptr, nullptr, i == xy_seq));
+                    HIP_TRY(launch_depth_tests(a, grid, s, nullptr, nullptr, depth_units(a, d + i)));
                 }
                 HIP_TRY(launch_depth_apply(a, s));
             }

@@ -164,10 +164,17 @@ __host__ __device__ bool small_search(const DepthArgs &a);
 hipError_t launch_depth_prepare(const DepthArgs &a, hipStream_t s);   // snapshot .. scatter
 // With start/stop events the runtime records them with the kernel's own
 // dispatch (tight bracketing of short kernels).
-// xy: the instance for a depth of (edge, level) units (depth 1 with
-// a.xy_policy set).
+// units: the instance for the depth's work units: 0 one test, 1 (edge, level)
+// groups (depth 1 with a.xy_policy); the host's choice for a depth must match
+// depth_units().
 hipError_t launch_depth_tests(const DepthArgs &a, int grid, hipStream_t s,
-                              hipEvent_t start = nullptr, hipEvent_t stop = nullptr, bool xy = false);
+                              hipEvent_t start = nullptr, hipEvent_t stop = nullptr, int units = 0);
+// Work units of depth d (the rule the depth preparation applies).
+inline int depth_units(const DepthArgs &a, int d) {
+    if (a.edge_form || a.err_val) return 0;
+    if (a.xy_policy == 1 && d == 1 && a.round_width == 0) return 1;
+    return 0;
+}
 hipError_t launch_depth_apply(const DepthArgs &a, hipStream_t s);     // removals + finalize
 hipError_t launch_init_search(const DepthArgs &a, hipStream_t s);     // complete graph, reset
 hipError_t launch_publish(const DepthArgs &a, hipStream_t s);         // results into pinned host memory

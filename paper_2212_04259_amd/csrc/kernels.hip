@@ -981,30 +981,42 @@ BNS_INLINE uint64_t table_cells(const TestSh &t) {
 }
 
 // ---------------------------------------------------------------------------
-// Depth 1 in (edge, level) units: the ranks of one level of one edge differ
-// only in Z, so they are counted in one pass over the samples that loads the X
-// and Y columns once (Section IV-B groups the tests of an edge for the same
-// reason) and adds every test's own table; the tables' epilogues (replica
-// sums, marginals, statistic) run one table per wave, and the chi-square
-// tails one test per lane.  A pass holds up to kXY tests; a unit with more
-// runs in several passes and stops after the pass with the first acceptance.
+// Depth 1 in (edge, level) units: the ranks an edge has in one level of the
+// work queue differ only in Z, so they are counted in one pass over the
+// samples that loads the X and Y columns once (Section IV-B groups the tests
+// of an edge for the same reason) and adds every test's own table; their
+// epilogues then run together: one table per wave (replica sums, marginals,
+// statistic, df) and one chi-square tail per lane.  A pass holds up to kXY
+// tests; a unit with more runs in several passes and stops after the pass
+// with the first acceptance.
 // ---------------------------------------------------------------------------
 constexpr int kXY = 8;
+constexpr int kPassCols = 3;  // x, y, z
 
-// Descriptor of a pass, at the start of the group's LDS region.
-struct XYHdr {
-    const uint8_t *zcol[kXY];
+struct PassTest {
+    const uint8_t *col[kPassCols];
+    uint32_t mult[kPassCols];
+    int32_t ncols;
+    uint32_t rx, ry, nz;  // cardinalities of X and Y, strata (prod r_Z)
+    int64_t e;            // edge record
+    uint64_t r;           // rank
+    int64_t m;
+    double alpha;
+};
+
+// Descriptor of a pass, at an 8-byte boundary of the group's LDS region.
+struct PassHdr {
+    PassTest t[kXY];
     double g2[kXY];
     double df[kXY];
-    uint32_t rz[kXY];
-    uint32_t toff[kXY];   // word offset of test t's replicated counts after the header
+    uint32_t toff[kXY];   // word offset of test i's replicated counts after the header
     uint32_t roff[kXY];   // word offset of its summed table (= toff when not replicated)
     uint32_t moff[kXY];   // word offset of its marginals: rows, columns, strata
     int32_t flag[kXY];    // FP64 re-check requests
     int32_t first;        // first accepting test of the pass (kXY: none)
     int32_t pad;
 };
-constexpr uint32_t kXYHdrWords = (uint32_t)((sizeof(XYHdr) + 15) / 16 * 4);
+constexpr uint32_t kPassHdrWords = (uint32_t)((sizeof(PassHdr) + 15) / 16 * 4);
 
 struct XYOut {
     int32_t first_accept;  // offset in the unit of its first accepting test, -1: none
@@ -1020,9 +1032,137 @@ BNS_INLINE double chi2_dens_lane(double df, double g2) {
     return exp((a - 1.0) * log(x) - x - lgamma(a));
 }
 
-// Counts kb tables of one pass: table t at byte offset b_t (+4 replica)
-// counts cell x + rx y + rx ry z_t; two samples per register (as count_packed).
-BNS_INLINE void count_xy(const uint8_t *xc, const uint8_t *yc, const XYHdr &h, uint32_t tab_lo, int kb,
+BNS_INLINE PassHdr &pass_hdr(uint32_t *region, uint32_t **tabs) {
+    uint32_t *hreg = region + ((lds_offset(region) >> 2) & 1u);
+    *tabs = hreg + kPassHdrWords;
+    return *(PassHdr *)hreg;
+}
+
+// The most tests of the pass (and then the most replication) whose tables
+// fit wt words with 16-bit byte addresses; cells[i]: test i's cells.
+BNS_INLINE void pass_plan(const uint32_t (&cells)[kXY], const uint32_t (&marg)[kXY], int kmax, uint32_t wt,
+                          uint32_t tab_lo, int max_rep_log2, int64_t msamp, int S, int *kb_out, int *logR_out) {
+    int kb = kmax, logR = max_rep_log2;
+    for (;;) {
+        uint32_t rep_w = 0, red_w = 0, mar_w = 0, cmax = 0;
+#pragma unroll
+        for (int i = 0; i < kXY; ++i)
+            if (i < kb) {
+                rep_w += cells[i] << logR;
+                red_w += logR > 0 ? cells[i] : 0u;
+                mar_w += marg[i];
+                cmax = max(cmax, cells[i]);
+            }
+        const bool fits = (uint64_t)rep_w + red_w + mar_w <= wt && (uint64_t)tab_lo + 4ull * rep_w <= 65536ull;
+        const bool cheap = logR == 0 || ((int64_t)(cmax << logR) * 4 <= msamp + 16 * S);
+        if (fits && cheap) break;
+        if (logR > 0) --logR;
+        else if (--kb == 0) break;
+    }
+    *kb_out = kb;
+    *logR_out = logR;
+}
+
+// Layout of a pass (lane 0): replicated tables, then per test its summed
+// table (when replicated) and its marginals.
+BNS_INLINE void pass_layout(PassHdr &h, const uint32_t (&cells)[kXY], const uint32_t (&marg)[kXY], int kb,
+                            int logR) {
+    uint32_t off = 0;
+    for (int i = 0; i < kb; ++i) {
+        h.toff[i] = off;
+        off += cells[i] << logR;
+    }
+    for (int i = 0; i < kb; ++i) {
+        h.roff[i] = h.toff[i];
+        if (logR > 0) {
+            h.roff[i] = off;
+            off += cells[i];
+        }
+        h.moff[i] = off;
+        off += marg[i];
+    }
+    h.first = kXY;
+}
+
+// Epilogue of a counted pass: per test (one wave each) replica sums,
+// marginals, statistic and df; then per test (lane i of the group) the tail,
+// an FP64 re-check near alpha from the resident table, and the decision.
+// Returns the acceptance of test g.rank (lanes below kb) and, uniform, the
+// number of re-checked tests.
+template <bool kGeneral>
+BNS_INLINE bool pass_finish(const Grp &g, PassHdr &h, uint32_t *tabs, int kb, int logR, const Tile &tile,
+                            int *nflag_out) {
+    const int nw = g.block ? kWaves : 1;
+    const int wv = g.block ? (int)(threadIdx.x >> 6) : 0;
+    const int lane = (int)(threadIdx.x & 63);
+    const Grp wg = Grp::wave();
+    const int stat = kGeneral ? tile.stat : 0;
+    const bool adj = kGeneral && tile.df_rule != 0;
+    const bool fp64 = tile.fp64 != 0;
+    for (int i = wv; i < kb; i += nw) {
+        const uint32_t rx = h.t[i].rx, ry = h.t[i].ry, nz = h.t[i].nz;
+        const uint32_t Tc = rx * ry * nz;
+        uint32_t *red = tabs + h.roff[i];
+        if (logR > 0) {
+            reduce_replicas(tabs + h.toff[i], red, Tc, logR, lane, 64);
+            wg.sync();
+        }
+        uint32_t *rows = tabs + h.moff[i], *cols = rows + rx * nz, *strata = cols + ry * nz;
+        marginals(wg, red, rows, cols, strata, rx, ry, nz);
+        double st;
+        if (fp64) st = wave_sum(stat_partial<double>(wg, red, rows, cols, strata, rx, ry, nz, stat));
+        else st = (double)wave_sum(stat_partial<float>(wg, red, rows, cols, strata, rx, ry, nz, stat));
+        const double dfv = adj ? wave_sum(adj_df_partial(wg, rows, cols, strata, rx, ry, nz))
+                               : (double)(rx - 1) * (double)(ry - 1) * (double)nz;
+        if (lane == 0) {
+            h.g2[i] = stat ? st : 2.0 * st;
+            h.df[i] = dfv;
+        }
+    }
+    g.sync();
+    bool acc = false;
+    if (g.rank < kb) {
+        const PassTest &q = h.t[g.rank];
+        const double x = h.g2[g.rank], df = h.df[g.rank];
+        const double p = chi2_tail_lane((int64_t)df, x);
+        int flag = 0;
+        if (!fp64 && df > 0.0) {
+            const double gap = fabs(p - q.alpha);
+            const double cells = (double)q.rx * (double)q.ry * (double)q.nz;
+            const double rel = (32.0 + cells / 64.0 + 1.0) * 5.96e-8 + 1e-6;
+            const double dp = chi2_dens_lane(df, x) * 0.5 * x * rel;
+            if (gap < tile.band || gap < 4.0 * dp) flag = 1;
+        }
+        h.flag[g.rank] = flag;
+        acc = !flag && p > q.alpha;
+    }
+    g.sync();
+    int nflag = 0;
+#pragma unroll
+    for (int i = 0; i < kXY; ++i)
+        if (i < kb) nflag += h.flag[i];
+    nflag = uni(nflag);
+    if (nflag > 0) {
+        for (int i = wv; i < kb; i += nw) {
+            if (!h.flag[i]) continue;
+            const uint32_t rx = h.t[i].rx, ry = h.t[i].ry, nz = h.t[i].nz;
+            const uint32_t *red = tabs + h.roff[i];
+            const uint32_t *rows = tabs + h.moff[i], *cols = rows + rx * nz, *strata = cols + ry * nz;
+            const double st = wave_sum(stat_partial<double>(wg, red, rows, cols, strata, rx, ry, nz, stat));
+            if (lane == 0) h.g2[i] = stat ? st : 2.0 * st;
+        }
+        g.sync();
+        if (g.rank < kb && h.flag[g.rank])
+            acc = chi2_tail_lane((int64_t)h.df[g.rank], h.g2[g.rank]) > h.t[g.rank].alpha;
+    }
+    *nflag_out = nflag;
+    return acc;
+}
+
+// Counts kb tables of one (edge, level) pass: table t at byte offset bt_t
+// (+4 replica) counts cell x + rx y + rx ry z_t; two samples per register
+// (as count_packed).
+BNS_INLINE void count_xy(const uint8_t *xc, const uint8_t *yc, const PassHdr &h, uint32_t tab_lo, int kb,
                          uint32_t rx, uint32_t rxy, int logR, int64_t m, int rank, int S) {
     const uint32_t rep = (uint32_t)rank & ((1u << logR) - 1u);
     const uint32_t mx4 = __builtin_amdgcn_readfirstlane(1u << (logR + 2));
@@ -1034,7 +1174,7 @@ BNS_INLINE void count_xy(const uint8_t *xc, const uint8_t *yc, const XYHdr &h, u
 #pragma unroll
     for (int t = 0; t < kXY; ++t) {
         bt[t] = __builtin_amdgcn_readfirstlane(tab_lo + 4u * h.toff[t < kb ? t : 0]);
-        cz[t] = uniform_col(h.zcol[t < kb ? t : 0]);
+        cz[t] = uniform_col(h.t[t < kb ? t : 0].col[2]);
     }
     const uint32_t rep4 = 4u * rep, rep2 = rep4 | (rep4 << 16);
     const gvec4 *cx = uniform_col(xc), *cy = uniform_col(yc);
@@ -1079,15 +1219,12 @@ BNS_INLINE void count_xy(const uint8_t *xc, const uint8_t *yc, const XYHdr &h, u
 
 // Ranks q.r .. q.r + q.xyk - 1 of edge q.e at depth 1 (all lanes of the group).
 template <bool kGeneral>
-BNS_INLINE XYOut run_xy_unit(const Grp &g, TestSh &t, uint32_t *region, uint32_t W, const Tile &tile,
-                             const DepthArgs &A, const Desc &q) {
-    (void)t;
+BNS_INLINE XYOut run_xy_unit(const Grp &g, uint32_t *region, uint32_t W, const Tile &tile, const DepthArgs &A,
+                             const Desc &q) {
     XYOut o{-1, 0u, 0u, kDevOk};
-    // the header at an 8-byte boundary, the tables after it
-    uint32_t *hreg = region + ((lds_offset(region) >> 2) & 1u);
-    XYHdr &h = *(XYHdr *)hreg;
-    uint32_t *tabs = hreg + kXYHdrWords;
-    const uint32_t Wt = W > kXYHdrWords + 1u ? W - kXYHdrWords - 1u : 0u;
+    uint32_t *tabs;
+    PassHdr &h = pass_hdr(region, &tabs);
+    const uint32_t Wt = W > kPassHdrWords + 1u ? W - kPassHdrWords - 1u : 0u;
     const uint32_t rx = uni((uint32_t)q.card[0]), ry = uni((uint32_t)q.card[1]), rxy = rx * ry;
     const int64_t m = uni(q.m);
     const int64_t e = uni(q.e);
@@ -1095,17 +1232,9 @@ BNS_INLINE XYOut run_xy_unit(const Grp &g, TestSh &t, uint32_t *region, uint32_t
     const uint32_t k = uni(q.xyk);
     const EdgeRec rec = A.edges[e];
     const ProbDev P = A.probs[uni(q.prob)];
-    const int stat = kGeneral ? tile.stat : 0;
-    const bool adj = kGeneral && tile.df_rule != 0;
-    const bool fp64 = tile.fp64 != 0;
-    const double alpha = uni(q.alpha);
     const uint8_t *xc = uni(q.data + (int64_t)q.var[0] * q.ld);
     const uint8_t *yc = uni(q.data + (int64_t)q.var[1] * q.ld);
     const uint32_t tab_lo = lds_offset(tabs);
-    const int nw = g.block ? kWaves : 1;
-    const int wv = g.block ? (int)(threadIdx.x >> 6) : 0;
-    const int lane = (int)(threadIdx.x & 63);
-    const Grp wg = Grp::wave();
     uint32_t b0 = 0;
     while (b0 < k) {
         if (b0 > 0) {
@@ -1123,119 +1252,39 @@ BNS_INLINE XYOut run_xy_unit(const Grp &g, TestSh &t, uint32_t *region, uint32_t
             const int skip = sideA ? rec.posj : rec.posi;
             const int pos = (int)(sideA ? r : r - rec.nA);
             const int z = A.nbr[P.adj_off + (int64_t)owner * P.n + pos + (pos >= skip ? 1 : 0)];
-            h.zcol[g.rank] = P.data + (int64_t)z * P.ld;
-            h.rz[g.rank] = A.cards[P.var_off + z];
+            PassTest &pt = h.t[g.rank];
+            pt.col[2] = P.data + (int64_t)z * P.ld;
+            pt.rx = rx;
+            pt.ry = ry;
+            pt.nz = A.cards[P.var_off + z];
+            pt.alpha = P.alpha;
         }
         g.sync();
-        // plan: the most tests (and then the most replication) whose tables
-        // fit the region with 16-bit byte addresses
-        uint32_t rz[kXY];
+        uint32_t cells[kXY], marg[kXY];
 #pragma unroll
-        for (int i = 0; i < kXY; ++i) rz[i] = i < (int)kmax ? uni(h.rz[i]) : 0u;
-        int kb = (int)kmax, logR = tile.max_rep_log2;
-        for (;;) {
-            uint32_t rep_w = 0, red_w = 0, mar_w = 0, cmax = 0;
-#pragma unroll
-            for (int i = 0; i < kXY; ++i)
-                if (i < kb) {
-                    rep_w += (rxy * rz[i]) << logR;
-                    red_w += logR > 0 ? rxy * rz[i] : 0u;
-                    mar_w += (rx + ry + 1u) * rz[i];
-                    cmax = max(cmax, rxy * rz[i]);
-                }
-            const bool fits = rep_w + red_w + mar_w <= Wt && tab_lo + 4u * rep_w <= 65536u;
-            const bool cheap = logR == 0 || ((int64_t)(cmax << logR) * 4 <= m + 16 * g.size);
-            if (fits && cheap) break;
-            if (logR > 0) --logR;
-            else if (--kb == 0) break;
+        for (int i = 0; i < kXY; ++i) {
+            const uint32_t nz = i < (int)kmax ? uni(h.t[i].nz) : 0u;
+            cells[i] = rxy * nz;
+            marg[i] = (rx + ry + 1u) * nz;
         }
+        int kb, logR;
+        pass_plan(cells, marg, (int)kmax, Wt, tab_lo, tile.max_rep_log2, m, g.size, &kb, &logR);
         if (kb == 0) {
             o.err = kDevTableTooLarge;
             return o;
         }
-        // layout: replicated tables, then per test its summed table (when
-        // replicated) and its marginals
-        if (g.rank == 0) {
-            uint32_t off = 0;
-            for (int i = 0; i < kb; ++i) {
-                h.toff[i] = off;
-                off += (rxy * rz[i]) << logR;
-            }
-            for (int i = 0; i < kb; ++i) {
-                h.roff[i] = h.toff[i];
-                if (logR > 0) {
-                    h.roff[i] = off;
-                    off += rxy * rz[i];
-                }
-                h.moff[i] = off;
-                off += (rx + ry + 1u) * rz[i];
-            }
-            h.first = kXY;
-        }
+        if (g.rank == 0) pass_layout(h, cells, marg, kb, logR);
         uint32_t rep_words = 0;
 #pragma unroll
         for (int i = 0; i < kXY; ++i)
-            if (i < kb) rep_words += (rxy * rz[i]) << logR;
+            if (i < kb) rep_words += cells[i] << logR;
         g.sync();
         for (uint32_t i = (uint32_t)g.rank; i < rep_words; i += (uint32_t)g.size) tabs[i] = 0u;
         g.sync();
         count_xy(xc, yc, h, tab_lo, kb, rx, rxy, logR, m, g.rank, g.size);
         g.sync();
-        // per test: replica sums, marginals, statistic, df (one wave per test)
-        for (int i = wv; i < kb; i += nw) {
-            const uint32_t Tc = rxy * rz[i];
-            const uint32_t *rep_t = tabs + h.toff[i];
-            uint32_t *red = tabs + h.roff[i];
-            if (logR > 0) {
-                reduce_replicas(rep_t, red, Tc, logR, lane, 64);
-                wg.sync();
-            }
-            uint32_t *rows = tabs + h.moff[i], *cols = rows + rx * rz[i], *strata = cols + ry * rz[i];
-            marginals(wg, red, rows, cols, strata, rx, ry, rz[i]);
-            double st;
-            if (fp64) st = wave_sum(stat_partial<double>(wg, red, rows, cols, strata, rx, ry, rz[i], stat));
-            else st = (double)wave_sum(stat_partial<float>(wg, red, rows, cols, strata, rx, ry, rz[i], stat));
-            const double dfv = adj ? wave_sum(adj_df_partial(wg, rows, cols, strata, rx, ry, rz[i]))
-                                   : (double)(rx - 1) * (double)(ry - 1) * (double)rz[i];
-            if (lane == 0) {
-                h.g2[i] = stat ? st : 2.0 * st;
-                h.df[i] = dfv;
-            }
-        }
-        g.sync();
-        // tails (lane i of the group), FP64 re-checks near alpha
-        bool acc = false;
-        int flag = 0;
-        if (g.rank < kb) {
-            const double x = h.g2[g.rank], df = h.df[g.rank];
-            const double p = chi2_tail_lane((int64_t)df, x);
-            if (!fp64 && df > 0.0) {
-                const double gap = fabs(p - alpha);
-                const double rel = (32.0 + (double)(rxy * rz[g.rank]) / 64.0 + 1.0) * 5.96e-8 + 1e-6;
-                const double dp = chi2_dens_lane(df, x) * 0.5 * x * rel;
-                if (gap < tile.band || gap < 4.0 * dp) flag = 1;
-            }
-            h.flag[g.rank] = flag;
-            acc = !flag && p > alpha;
-        }
-        g.sync();
         int nflag = 0;
-#pragma unroll
-        for (int i = 0; i < kXY; ++i)
-            if (i < kb) nflag += h.flag[i];
-        nflag = uni(nflag);
-        if (nflag > 0) {
-            for (int i = wv; i < kb; i += nw) {
-                if (!h.flag[i]) continue;
-                const uint32_t *red = tabs + h.roff[i];
-                const uint32_t *rows = tabs + h.moff[i], *cols = rows + rx * rz[i], *strata = cols + ry * rz[i];
-                const double st = wave_sum(stat_partial<double>(wg, red, rows, cols, strata, rx, ry, rz[i], stat));
-                if (lane == 0) h.g2[i] = stat ? st : 2.0 * st;
-            }
-            g.sync();
-            if (g.rank < kb && h.flag[g.rank])
-                acc = chi2_tail_lane((int64_t)h.df[g.rank], h.g2[g.rank]) > alpha;
-        }
+        const bool acc = pass_finish<kGeneral>(g, h, tabs, kb, logR, tile, &nflag);
         if (acc) atomicMin(&h.first, g.rank);
         g.sync();
         const int first = h.first;
@@ -1317,9 +1366,9 @@ struct Batch {
 // its FP32 error logged); the timed searches use the other.
 // GENERAL: the instance for other statistics or df rules than G^2 with the
 // declared df.
-// XY: the instance for a depth of (edge, level) units (run_xy_unit); a
-// separate instance keeps that path's registers out of the per-test one.
-template <int LGB, bool VERIFY, bool GENERAL, bool XY = false>
+// UNITS: the instance for a depth of (edge, level) units (1, run_xy_unit);
+// a separate instance keeps that path's registers out of the per-test one (0).
+template <int LGB, bool VERIFY, bool GENERAL, int UNITS = 0>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k_depth_tests(DepthArgs A) {
     extern __shared__ uint32_t lds[];
     __shared__ TestSh tsh[kWaves];
@@ -1383,7 +1432,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
     const long long Lc = uni(hdr.Lc);
     const uint64_t cap = uni(hdr.cap);
     const int mode = uni(hdr.mode);
-    if ((uni(hdr.xy) != 0) != XY) {
+    if (uni(hdr.xy) != UNITS) {
         if (blockIdx.x == 0 && threadIdx.x == 0) c->error = kDevUnitMismatch;
         return;
     }
@@ -1449,8 +1498,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
         for (int j = 0; j < cnt; ++j) {
             const Desc &q = mine[j];
             if (!uni(q.valid)) continue;
-            if constexpr (XY) {
-                const XYOut xo = run_xy_unit<GENERAL>(g, t, region, W, A.tile, A, q);
+            if constexpr (UNITS == 1) {
+                const XYOut xo = run_xy_unit<GENERAL>(g, region, W, A.tile, A, q);
                 if (g.rank == 0) {
                     tal_exec[ti] += xo.exec;
                     tal_re[ti] += xo.rechecks;
@@ -2032,11 +2081,11 @@ hipError_t launch_depth_prepare(const DepthArgs &a, hipStream_t s) {
 
 // Instance for the search: tickets dealt in runs when its columns exceed the
 // last-level cache's share (grab_block_log2 = kGrabRunLog2), else singly.
-static auto depth_tests_kernel(const DepthArgs &a, bool xy) -> decltype(&k_depth_tests<0, false, false>) {
+static auto depth_tests_kernel(const DepthArgs &a, int units) -> decltype(&k_depth_tests<0, false, false>) {
     const bool general = a.tile.stat != 0 || a.tile.df_rule != 0;
-    if (xy) {
-        if (general) return &k_depth_tests<0, false, true, true>;
-        return a.grab_block_log2 ? &k_depth_tests<kGrabRunLog2, false, false, true> : &k_depth_tests<0, false, false, true>;
+    if (units == 1) {
+        if (general) return &k_depth_tests<0, false, true, 1>;
+        return a.grab_block_log2 ? &k_depth_tests<kGrabRunLog2, false, false, 1> : &k_depth_tests<0, false, false, 1>;
     }
     // verification and other statistics: single-ticket dealing (the dealing
     // never changes results)
@@ -2046,8 +2095,8 @@ static auto depth_tests_kernel(const DepthArgs &a, bool xy) -> decltype(&k_depth
 }
 
 hipError_t launch_depth_tests(const DepthArgs &a, int grid, hipStream_t s, hipEvent_t start,
-                              hipEvent_t stop, bool xy) {
-    auto kern = depth_tests_kernel(a, xy);
+                              hipEvent_t stop, int units) {
+    auto kern = depth_tests_kernel(a, units);
     if (a.edge_form) kern = (a.tile.stat != 0 || a.tile.df_rule != 0) ? &k_depth_edges<true> : &k_depth_edges<false>;
     if (start && stop)
         hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kWG), (size_t)a.tile.lds_words * 4u, s, start, stop, 0, a);
@@ -2066,9 +2115,9 @@ hipError_t allow_dynamic_lds(int bytes) {
     const void *fns[] = {(const void *)k_depth_tests<kGrabRunLog2, false, false>,
                          (const void *)k_depth_tests<0, false, false>, (const void *)k_depth_tests<0, true, false>,
                          (const void *)k_depth_tests<0, false, true>, (const void *)k_depth_tests<0, true, true>,
-                         (const void *)k_depth_tests<0, false, false, true>,
-                         (const void *)k_depth_tests<kGrabRunLog2, false, false, true>,
-                         (const void *)k_depth_tests<0, false, true, true>,
+                         (const void *)k_depth_tests<0, false, false, 1>,
+                         (const void *)k_depth_tests<kGrabRunLog2, false, false, 1>,
+                         (const void *)k_depth_tests<0, false, true, 1>,
                          (const void *)k_depth_edges<false>, (const void *)k_depth_edges<true>};
     hipError_t e = hipSuccess;
     for (const void *f : fns)

@@ -108,3 +108,4 @@ def test_edge_units_tickets_count_edges_per_level(bns):
     assert got.stats[1]["tests_required"] == base.stats[1]["tests_required"]
     for d in (0, 2):
         assert got.stats[d]["tickets"] == base.stats[d]["tickets"]
+
