@@ -174,6 +174,7 @@ struct DevCtx {
     DevBuf tri_node, tri_rowoff, tri_eidx, tri_part;  // depth 1 through the masked contractions
     DevBuf pairs_setup, pairs_out;  // bns_ci_pairs: tile plan and results
     DevBuf err_val, err_tag, err_cnt;  // verification log
+    std::vector<uint64_t> binom_host;  // C(n, k) rows built so far (host)
     // bytes of the last search set-up uploaded into `setup` (a repeated
     // search skips the upload)
     std::vector<char> setup_last;
@@ -804,6 +805,7 @@ extern "C" int32_t bns_skeleton_n_vars(const bns_skeleton *sk) { return sk ? sk-
 
 extern "C" bns_status bns_skeleton_adjacency(const bns_skeleton *sk, uint8_t *adj) {
     if (!sk || !adj) return fail(BNS_E_INVALID_ARG, "NULL argument");
+    sk->expand();
     std::memcpy(adj, sk->adj.data(), sk->adj.size());
     return BNS_OK;
 }
@@ -814,6 +816,7 @@ extern "C" bns_status bns_skeleton_sepset(const bns_skeleton *sk, int32_t i, int
     if (!sk || !len) return fail(BNS_E_INVALID_ARG, "NULL argument");
     if (i < 0 || j < 0 || i >= sk->n || j >= sk->n || i == j) return fail(BNS_E_INVALID_ARG, "bad pair");
     if (cap < 0 || (cap > 0 && !members)) return fail(BNS_E_INVALID_ARG, "bad members buffer");
+    sk->expand();
     const int64_t ij = (int64_t)i * sk->n + j;
     const int32_t d = sk->depth[ij];
     if (removal_depth) *removal_depth = d;
@@ -831,6 +834,7 @@ extern "C" bns_status bns_skeleton_removals(const bns_skeleton *sk, int32_t *dep
                                             int32_t *pool, int64_t pool_cap, int64_t *pool_len) {
     if (!sk) return fail(BNS_E_INVALID_ARG, "NULL skeleton");
     if (pool_cap < 0 || (pool_cap > 0 && !pool)) return fail(BNS_E_INVALID_ARG, "bad pool buffer");
+    sk->expand();
     if (depth) std::memcpy(depth, sk->depth.data(), sk->depth.size() * sizeof(int32_t));
     if (sep_off) std::memcpy(sep_off, sk->sepoff.data(), sk->sepoff.size() * sizeof(int64_t));
     if (pool) std::memcpy(pool, sk->pool.data(), sizeof(int32_t) * (size_t)std::min<int64_t>(pool_cap, (int64_t)sk->pool.size()));
@@ -993,9 +997,16 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
         if (maxd[k] < 0) unbounded = true;
         dmax = std::max(dmax, maxd[k]);
     }
-    std::vector<uint64_t> B;
+    // binomial table (rebuilt only when a search needs more rows)
     const int brows = nmax + 1;
-    build_binom(brows, B);
+    if ((int)(dc.binom_host.size() / kBinomK) < brows) build_binom(brows, dc.binom_host);
+    const std::vector<uint64_t> &Bfull = dc.binom_host;
+    struct BView {
+        const uint64_t *p;
+        size_t n;
+        size_t size() const { return n; }
+        const uint64_t *data() const { return p; }
+    } B{Bfull.data(), (size_t)brows * kBinomK};
 
     // One packed upload: problems, variable -> problem map, cardinalities,
     // binomial table (8-byte aligned sections).
@@ -1452,16 +1463,7 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
         const int n = ds[k]->n;
         const int64_t base = probs[k].adj_off, nn = (int64_t)n * n;
         sk->n = n;
-        sk->adj.resize((size_t)nn);
-        sk->depth.resize((size_t)nn);
-        sk->sepoff.assign((size_t)nn, -1);
-        for (int64_t i = 0, e = 0; i < n; ++i)
-            for (int64_t j = 0; j < n; ++j, ++e) {
-                const int8_t dd = hdep[base + e];
-                sk->depth[e] = dd;
-                sk->adj[e] = (dd < 0 && i != j) ? 1 : 0;
-                if (dd == 0) sk->sepoff[e] = 0;  // empty set
-            }
+        sk->rdep.assign(hdep + base, hdep + base + nn);
         if (!per_prob) {
             sk->stats = stats;
             for (size_t dd = 0; dd < sk->stats.size(); ++dd) fill_err(sk->stats[dd], k, (int)dd);
@@ -1489,12 +1491,12 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
         if (k < 0 || k >= P) return fail(BNS_E_INTERNAL, "corrupt removal record");
         bns_skeleton *sk = sks[k].get();
         const int n = sk->n;
-        const int32_t dd = sk->depth[(int64_t)i * n + j];
+        if (i < 0 || j < 0 || i >= n || j >= n) return fail(BNS_E_INTERNAL, "corrupt removal record");
+        const int32_t dd = sk->rdep[(size_t)((int64_t)i * n + j)];
         if (dd <= 0) return fail(BNS_E_INTERNAL, "removal record for a pair not removed at depth >= 1");
-        const int64_t off = (int64_t)sk->pool.size();
+        sk->rec_pair.push_back((int64_t)i * n + j);
+        sk->rec_off.push_back((int64_t)sk->pool.size());
         sk->pool.insert(sk->pool.end(), hpool + q + 3, hpool + q + 3 + dd);
-        sk->sepoff[(int64_t)i * n + j] = off;
-        sk->sepoff[(int64_t)j * n + i] = off;
         q += (unsigned long long)dd + 3;
     }
     for (int32_t k = 0; k < P; ++k) outs[k] = sks[k].release();
@@ -1551,6 +1553,7 @@ static bns_status run_plain(DevCtx &dc, const bns_dataset *ds, double alpha, int
     hipStream_t s = o.stream ? (hipStream_t)o.stream : dc.stream;
     const int n = ds->n;
     std::unique_ptr<bns_skeleton> sk(new bns_skeleton());
+    sk->full = true;
     sk->n = n;
     sk->adj.assign((size_t)n * n, 0);
     sk->depth.assign((size_t)n * n, -1);

@@ -39,6 +39,7 @@ bool in_sepset(const bns_skeleton &sk, int x, int y, int z) {
 
 extern "C" bns_status bns_skeleton_orient(const bns_skeleton *sk, int8_t *cpdag) {
     if (!sk || !cpdag) return BNS_E_INVALID_ARG;
+    sk->expand();
     const int n = sk->n;
     Marks G{n, std::vector<int8_t>((size_t)n * n, 0)};
     // neighbour lists (ascending) of the skeleton
@@ -121,6 +122,7 @@ extern "C" bns_status bns_skeleton_create(int32_t n, const uint8_t *adj, const i
     if (n < 2 || n > 65535 || !adj || !depth || !sep_off || pool_len < 0 || (pool_len > 0 && !pool))
         return BNS_E_INVALID_ARG;
     bns_skeleton *sk = new bns_skeleton();
+    sk->full = true;
     sk->n = n;
     const size_t nn = (size_t)n * n;
     sk->adj.assign(adj, adj + nn);
