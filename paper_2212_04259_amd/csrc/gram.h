@@ -1,6 +1,6 @@
 // Shared pieces of the one-hot Gram contractions on gfx950 int8 MFMA (depth
 // 0 over all variables, depth 1 over each node's neighbours under a mask):
-// operand types, pipeline constants and the one-hot expansion of uint8
+// operand types, the workgroup size and the one-hot expansion of uint8
 // columns.
 #pragma once
 
@@ -12,8 +12,6 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kGramWG = 256;
-constexpr int kKS = 64;         // samples per pipeline step (two MFMA k-steps of 32)
-constexpr int kRow = kKS + 16;  // LDS bytes per one-hot column and step (padding spreads banks)
 
 // One-hot bytes [b == cat] of the 16 samples in w; bytes at and beyond
 // nvalid are zero.  Variables of at most 8 categories take one byte permute

@@ -402,6 +402,7 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
         const uint32_t dbit = d < 32 ? 1u << d : 0u;
         const int mode = (A.block_depths & dbit) ? 1
                        : (A.wave_depths & dbit)  ? 0
+                       : xy                      ? 1  // (edge, level) units: a wave's LDS share holds few tables
                        : (A.mode_policy == 2)    ? 1
                        : (A.mode_policy == 1)    ? 0
                        : (total >= kWaveModeRounds * tw * (d >= kWaveModeDeepDepth ? 2ull : 1ull)) ? 0

@@ -25,16 +25,20 @@
 
 namespace bns {
 
+constexpr int kGramKS = 64;             // samples per pipeline step
+constexpr int kGramRow = kGramKS + 16;  // LDS bytes per one-hot column and step
+constexpr int kGramQS = kGramKS / 16;   // 16-sample groups per column and step
+
 // c: the search's control block (its done flag, the depth's start stamp), or
 // null for the all-pairs entry point.
 template <int T>
 __global__ __launch_bounds__(kGramWG) void k_gram(PairArgs P, Ctl *c) {
     constexpr int WT = T / 2;              // rows (and columns) of a wave's block
     constexpr int NF = WT / 32;            // 32 x 32 MFMA tiles per side of a wave's block
-    constexpr int kTasks = 2 * T * (kKS / 16);  // (operand, column, 16-sample group) per step
+    constexpr int kTasks = 2 * T * kGramQS;  // (operand, column, 16-sample group) per step
     constexpr int kPer = kTasks / kGramWG;
     static_assert(kPer * kGramWG == kTasks, "tasks split evenly");
-    __shared__ __attribute__((aligned(16))) uint8_t lds[2][2 * T * kRow];  // [buffer][operand][column][sample]
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2][2 * T * kGramRow];  // [buffer][operand][column][sample]
     __shared__ int quit;
     if (threadIdx.x == 0) {
         quit = c ? c->done : 0;
@@ -72,7 +76,7 @@ __global__ __launch_bounds__(kGramWG) void k_gram(PairArgs P, Ctl *c) {
         const bool diag = tr == tc;  // the second operand is the first
         const int64_t s0 = (int64_t)kc * P.chunk;
         const int64_t s1 = min(gp.m, s0 + P.chunk);
-        const int nsteps = (int)((s1 - s0 + kKS - 1) / kKS);
+        const int nsteps = (int)((s1 - s0 + kGramKS - 1) / kGramKS);
         // this thread's expansion tasks for every step of the item
         const uint8_t *colp[kPer];
         uint32_t plo[kPer], phi[kPer], cat[kPer];
@@ -81,11 +85,11 @@ __global__ __launch_bounds__(kGramWG) void k_gram(PairArgs P, Ctl *c) {
 #pragma unroll
         for (int r = 0; r < kPer; ++r) {
             const int id = tid + kGramWG * r;
-            const int op = id / (T * 4);
-            const int rest = id - op * T * 4;
-            const int col = rest >> 2, q = rest & 3;
+            const int op = id / (T * kGramQS);
+            const int rest = id - op * T * kGramQS;
+            const int col = rest / kGramQS, q = rest % kGramQS;
             act[r] = !(diag && op == 1);
-            dst[r] = op * T * kRow + col * kRow + 16 * q;
+            dst[r] = op * T * kGramRow + col * kGramRow + 16 * q;
             const int gcol = (op ? tc : tr) * T + col;
             const int v = P.oh_var[gp.oh_base + gcol];
             const uint32_t cb = P.oh_cat[gp.oh_base + gcol];
@@ -100,7 +104,7 @@ __global__ __launch_bounds__(kGramWG) void k_gram(PairArgs P, Ctl *c) {
         auto load = [&](int64_t s) {
 #pragma unroll
             for (int r = 0; r < kPer; ++r) {
-                const int64_t ss = s + 16 * ((tid + kGramWG * r) & 3);
+                const int64_t ss = s + 16 * ((tid + kGramWG * r) % kGramQS);
                 pn[r] = (int)max((int64_t)0, min((int64_t)16, s1 - ss));
                 pv[r] = u32x4{0u, 0u, 0u, 0u};
                 if (act[r] && colp[r] && pn[r] > 0) pv[r] = *(const u32x4 *)(colp[r] + s);
@@ -128,19 +132,19 @@ __global__ __launch_bounds__(kGramWG) void k_gram(PairArgs P, Ctl *c) {
         for (int st = 0; st < nsteps; ++st) {
             const int buf = st & 1;
             const bool more = st + 1 < nsteps;
-            if (more) load(s0 + (int64_t)(st + 1) * kKS);
+            if (more) load(s0 + (int64_t)(st + 1) * kGramKS);
             const uint8_t *La = &lds[buf][0];
-            const uint8_t *Lb = diag ? La : &lds[buf][T * kRow];
+            const uint8_t *Lb = diag ? La : &lds[buf][T * kGramRow];
 #pragma unroll
-            for (int kk = 0; kk < 2; ++kk) {
+            for (int kk = 0; kk < kGramKS / 32; ++kk) {
                 const int koff = 32 * kk + 16 * (lane >> 5);
                 v4i af[NF], bf[NF];
 #pragma unroll
                 for (int i = 0; i < NF; ++i)
-                    af[i] = *(const v4i *)(La + (wr * WT + 32 * i + (lane & 31)) * kRow + koff);
+                    af[i] = *(const v4i *)(La + (wr * WT + 32 * i + (lane & 31)) * kGramRow + koff);
 #pragma unroll
                 for (int j = 0; j < NF; ++j)
-                    bf[j] = *(const v4i *)(Lb + (wc * WT + 32 * j + (lane & 31)) * kRow + koff);
+                    bf[j] = *(const v4i *)(Lb + (wc * WT + 32 * j + (lane & 31)) * kGramRow + koff);
 #pragma unroll
                 for (int i = 0; i < NF; ++i)
 #pragma unroll
