@@ -1015,7 +1015,7 @@ struct PassHdr {
     uint32_t moff[kXY];   // word offset of its marginals: rows, columns, strata
     int32_t flag[kXY];    // FP64 re-check requests
     int32_t first;        // first accepting test of the pass (kXY: none)
-    int32_t pad;
+    int32_t stop;         // the unit's remaining ranks are not needed (group-wide decision)
 };
 constexpr uint32_t kPassHdrWords = (uint32_t)((sizeof(PassHdr) + 15) / 16 * 4);
 
@@ -1239,10 +1239,16 @@ BNS_INLINE XYOut run_xy_unit(const Grp &g, uint32_t *region, uint32_t W, const T
     uint32_t b0 = 0;
     while (b0 < k) {
         if (b0 > 0) {
-            // a lower rank of the edge has accepted: the rest are not needed
-            const unsigned long long ma = uni(
-                __hip_atomic_load(&A.min_accept[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            if (ma < r0 + b0) break;
+            // a lower rank of the edge has accepted: the rest are not needed.
+            // One lane reads the edge's first-accept rank and the group takes
+            // its decision from LDS (waves reading it on their own could see
+            // different values and part at the next barrier).
+            if (g.rank == 0)
+                h.stop = __hip_atomic_load(&A.min_accept[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < r0 + b0;
+            g.sync();
+            // (lane 0 rewrites h.stop only after the pass's barriers, which
+            // every lane reaches after this read)
+            if (h.stop) break;
         }
         const uint32_t kmax = min((uint32_t)kXY, k - b0);
         // the pass's conditioning variables: rank r0 + b0 + i (lanes i)
