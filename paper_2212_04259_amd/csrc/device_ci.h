@@ -642,18 +642,32 @@ BNS_INLINE void count_range(const TestSh &t, uint32_t *tab, uint32_t cbase, uint
 BNS_INLINE void reduce_replicas(const uint32_t *rep_tab, uint32_t *out, uint32_t Tc, int logR,
                                 int rank, int S) {
     const uint32_t R = 1u << logR, mask = R - 1u;
-    for (uint32_t c = (uint32_t)rank; c < Tc; c += (uint32_t)S) {
-        const uint32_t *p = rep_tab + (c << logR);
+    // L = 2^lgL lanes per cell when the cells leave lanes idle: each sums
+    // R / L (at least 4) replicas and the L partial sums (consecutive lanes
+    // of one wave) are combined with lane exchanges.
+    int lgL = 0;
+    while (lgL < 6 && (Tc << (lgL + 1)) <= (uint32_t)S && (8u << lgL) <= R) ++lgL;
+    const uint32_t span = R >> lgL;
+    const uint32_t j = (uint32_t)rank & ((1u << lgL) - 1u);
+    for (uint32_t c0 = 0; c0 < Tc; c0 += (uint32_t)S >> lgL) {
+        const uint32_t c = c0 + ((uint32_t)rank >> lgL);
         uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-        uint32_t r = 0;
-        for (; r + 4 <= R; r += 4) {
-            s0 += p[(r + c) & mask];
-            s1 += p[(r + 1 + c) & mask];
-            s2 += p[(r + 2 + c) & mask];
-            s3 += p[(r + 3 + c) & mask];
+        if (c < Tc) {
+            // (replica r + c of cell c: neighbouring cells start on different banks)
+            const uint32_t *p = rep_tab + (c << logR);
+            uint32_t r = j * span;
+            const uint32_t r1 = r + span;
+            for (; r + 4 <= r1; r += 4) {
+                s0 += p[(r + c) & mask];
+                s1 += p[(r + 1 + c) & mask];
+                s2 += p[(r + 2 + c) & mask];
+                s3 += p[(r + 3 + c) & mask];
+            }
+            for (; r < r1; ++r) s0 += p[(r + c) & mask];
         }
-        for (; r < R; ++r) s0 += p[(r + c) & mask];
-        out[c] = (s0 + s1) + (s2 + s3);
+        uint32_t sum = (s0 + s1) + (s2 + s3);
+        for (int off = 1; off < (1 << lgL); off <<= 1) sum += (uint32_t)__shfl_xor((int)sum, off, 64);
+        if (c < Tc && j == 0) out[c] = sum;
     }
 }
 
