@@ -604,7 +604,10 @@ BNS_INLINE void count_tail(const TestSh &t, uint32_t *tab, uint32_t cbase, uint3
 }
 
 // Counts samples [s0, s1) (s0 a multiple of 16) with the S lanes of a group.
-template <bool kChunk>
+// kNcMax: the most columns the instance specialises (tests of more columns
+// take the generic loop); an instance for shallow depths leaves out the wide
+// unrolled loops and the registers they hold.
+template <bool kChunk, int kNcMax = kMaxCols>
 BNS_INLINE void count_range(const TestSh &t, uint32_t *tab, uint32_t cbase, uint32_t Tc,
                             uint32_t trash, int logR, int64_t s0, int64_t s1, int rank, int S) {
     const int64_t q0 = s0 >> 4, q1 = s1 >> 4;
@@ -617,8 +620,14 @@ BNS_INLINE void count_range(const TestSh &t, uint32_t *tab, uint32_t cbase, uint
                 case 2: count_packed<2>(t, tab, logR, q0, q1, rank, S); break;
                 case 3: count_packed<3>(t, tab, logR, q0, q1, rank, S); break;
                 case 4: count_packed<4>(t, tab, logR, q0, q1, rank, S); break;
-                case 5: count_packed<5>(t, tab, logR, q0, q1, rank, S); break;
-                default: count_packed<6>(t, tab, logR, q0, q1, rank, S); break;
+                default:
+                    if constexpr (kNcMax >= 6) {
+                        if (nc == 5) count_packed<5>(t, tab, logR, q0, q1, rank, S);
+                        else count_packed<6>(t, tab, logR, q0, q1, rank, S);
+                    } else {
+                        count_generic<false>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S);
+                    }
+                    break;
             }
         } else {
             count_generic<false>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S);
@@ -628,9 +637,19 @@ BNS_INLINE void count_range(const TestSh &t, uint32_t *tab, uint32_t cbase, uint
             case 2: count_fixed<2, true>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
             case 3: count_fixed<3, true>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
             case 4: count_fixed<4, true>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
-            case 5: count_fixed<5, true>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
-            case 6: count_fixed<6, true>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
-            default: count_generic<true>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S); break;
+            default:
+                if constexpr (kNcMax >= 6) {
+                    if (nc == 5) {
+                        count_fixed<5, true>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S);
+                        break;
+                    }
+                    if (nc == 6) {
+                        count_fixed<6, true>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S);
+                        break;
+                    }
+                }
+                count_generic<true>(t, tab, cbase, Tc, trash, logR, q0, q1, rank, S);
+                break;
         }
     }
     if ((q1 << 4) < s1) count_tail<kChunk>(t, tab, cbase, Tc, trash, logR, q1 << 4, s1, rank, S);
@@ -827,6 +846,7 @@ struct Src {
 // is computed.
 // The statistic is G^2 (stat 0) or X^2 (stat 1); with df_adj the adjusted
 // degrees of freedom of the table are summed into *df_adj.
+template <int kNcMax = kMaxCols>
 BNS_INLINE double table_pass(const Grp &g, TestSh &t, const Plan &P, uint32_t *lds, uint32_t *gtab,
                              const Src &src, bool fp64, const uint32_t **tab_out, int stat,
                              double *df_adj) {
@@ -869,9 +889,9 @@ BNS_INLINE double table_pass(const Grp &g, TestSh &t, const Plan &P, uint32_t *l
             for (uint32_t i = g.rank; i < head; i += g.size) rep_tab[i] = 0u;
             g.sync();
             if (chunked)
-                count_range<true>(t, rep_tab, P.rxy * z0, Tc, Tc, 0, src.s0, src.s1, g.rank, g.size);
+                count_range<true, kNcMax>(t, rep_tab, P.rxy * z0, Tc, Tc, 0, src.s0, src.s1, g.rank, g.size);
             else
-                count_range<false>(t, rep_tab, 0, Tc, 0, logR, src.s0, src.s1, g.rank, g.size);
+                count_range<false, kNcMax>(t, rep_tab, 0, Tc, 0, logR, src.s0, src.s1, g.rank, g.size);
             g.sync();
             if (logR > 0) {
                 reduce_replicas(rep_tab, red, Tc, logR, g.rank, g.size);
@@ -958,7 +978,7 @@ BNS_INLINE Tail group_tail(const Grp &g, int64_t df, double g2, TestSh &t) {
 // the chunk [s0, s1) is counted and added there; no G^2, no decision).
 // kGeneral: the statistic and df rule come from the tile; otherwise the
 // instance is fixed to G^2 with df from the declared cards.
-template <bool kVerify = false, bool kGeneral = true>
+template <bool kVerify = false, bool kGeneral = true, int kNcMax = kMaxCols>
 BNS_INLINE TestOut run_test(const Grp &g, TestSh &t, uint32_t *lds, uint32_t W, const Tile &tile,
                             double alpha, uint32_t *gtab, const Src &src) {
     TestOut o;
@@ -988,7 +1008,7 @@ BNS_INLINE TestOut run_test(const Grp &g, TestSh &t, uint32_t *lds, uint32_t W, 
     int64_t df = P.df;
     for (int round = 0; round < 2; ++round) {
         double dfa = 0.0;
-        g2 = table_pass(g, t, P, lds, round == 0 ? gtab : nullptr, src, fp64, &tab, stat,
+        g2 = table_pass<kNcMax>(g, t, P, lds, round == 0 ? gtab : nullptr, src, fp64, &tab, stat,
                         adj ? &dfa : nullptr);
         if (src.gdst) {  // merge only: no statistic, no decision
             o.g2 = 0.0;
@@ -1026,7 +1046,7 @@ BNS_INLINE TestOut run_test(const Grp &g, TestSh &t, uint32_t *lds, uint32_t W, 
         double g64 = g2, p64 = p;
         if (!fp64 && !(o.flags & 2) && df > 0) {
             if (P.nchunks == 1) g64 = stat_fp64_resident(g, t, P, tab, stat);
-            else g64 = table_pass(g, t, P, lds, nullptr, src, true, &tab, stat, nullptr);
+            else g64 = table_pass<kNcMax>(g, t, P, lds, nullptr, src, true, &tab, stat, nullptr);
             p64 = group_tail(g, df, g64, t).p;
         }
         o.g2_ref = g64;

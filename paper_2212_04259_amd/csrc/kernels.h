@@ -165,14 +165,17 @@ hipError_t launch_depth_prepare(const DepthArgs &a, hipStream_t s);   // snapsho
 // With start/stop events the runtime records them with the kernel's own
 // dispatch (tight bracketing of short kernels).
 // units: the instance for the depth's work units: 0 one test, 1 (edge, level)
-// groups (depth 1 with a.xy_policy); the host's choice for a depth must match
-// depth_units().
+// groups (depth 1 with a.xy_policy), 2 one test of at most kNarrowDepth + 2
+// columns (the instance without the wider counting loops, whose registers
+// otherwise spill); the host's choice for a depth must match depth_units().
 hipError_t launch_depth_tests(const DepthArgs &a, int grid, hipStream_t s,
                               hipEvent_t start = nullptr, hipEvent_t stop = nullptr, int units = 0);
+constexpr int kNarrowDepth = 2;
 // Work units of depth d (the rule the depth preparation applies).
 inline int depth_units(const DepthArgs &a, int d) {
     if (a.edge_form || a.err_val) return 0;
     if (a.xy_policy == 1 && d == 1 && a.round_width == 0) return 1;
+    if (d <= kNarrowDepth && a.tile.stat == 0 && a.tile.df_rule == 0) return 2;
     return 0;
 }
 hipError_t launch_depth_apply(const DepthArgs &a, hipStream_t s);     // removals + finalize

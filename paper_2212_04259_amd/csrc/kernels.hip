@@ -1375,6 +1375,8 @@ struct Batch {
 // declared df.
 // UNITS: the instance for a depth of (edge, level) units (1, run_xy_unit);
 // a separate instance keeps that path's registers out of the per-test one (0).
+// 2: the per-test instance for depths up to kNarrowDepth (tests of at most
+// four columns), without the wider counting loops (fewer spilled registers).
 template <int LGB, bool VERIFY, bool GENERAL, int UNITS = 0>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k_depth_tests(DepthArgs A) {
     extern __shared__ uint32_t lds[];
@@ -1439,7 +1441,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
     const long long Lc = uni(hdr.Lc);
     const uint64_t cap = uni(hdr.cap);
     const int mode = uni(hdr.mode);
-    if (uni(hdr.xy) != UNITS) {
+    if (uni(hdr.xy) != (UNITS == 1 ? 1 : 0) || (UNITS == 2 && d > kNarrowDepth)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) c->error = kDevUnitMismatch;
         return;
     }
@@ -1558,7 +1560,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
                 }
             }
             for (;;) {
-                const TestOut o = run_test<VERIFY, GENERAL>(g, t, region, W, A.tile, uni(q.alpha), nullptr, src);
+                const TestOut o = run_test<VERIFY, GENERAL, UNITS == 2 ? kNarrowDepth + 2 : kMaxCols>(
+                    g, t, region, W, A.tile, uni(q.alpha), nullptr, src);
                 if (g.rank == 0) tal_bytes[ti] += (double)q.ncols * (double)(src.s1 - src.s0);
                 if (src.gdst) {
                     // Every access to a merge table and its chunk counter is
@@ -2094,6 +2097,8 @@ static auto depth_tests_kernel(const DepthArgs &a, int units) -> decltype(&k_dep
         if (general) return &k_depth_tests<0, false, true, 1>;
         return a.grab_block_log2 ? &k_depth_tests<kGrabRunLog2, false, false, 1> : &k_depth_tests<0, false, false, 1>;
     }
+    if (units == 2 && !general && !a.err_val)
+        return a.grab_block_log2 ? &k_depth_tests<kGrabRunLog2, false, false, 2> : &k_depth_tests<0, false, false, 2>;
     // verification and other statistics: single-ticket dealing (the dealing
     // never changes results)
     if (a.err_val) return general ? &k_depth_tests<0, true, true> : &k_depth_tests<0, true, false>;
@@ -2125,6 +2130,8 @@ hipError_t allow_dynamic_lds(int bytes) {
                          (const void *)k_depth_tests<0, false, false, 1>,
                          (const void *)k_depth_tests<kGrabRunLog2, false, false, 1>,
                          (const void *)k_depth_tests<0, false, true, 1>,
+                         (const void *)k_depth_tests<0, false, false, 2>,
+                         (const void *)k_depth_tests<kGrabRunLog2, false, false, 2>,
                          (const void *)k_depth_edges<false>, (const void *)k_depth_edges<true>};
     hipError_t e = hipSuccess;
     for (const void *f : fns)
