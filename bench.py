@@ -397,6 +397,11 @@ def main():
     req_bytes = sum(req_bytes_d)
     ops_rate = req_bytes / span if span > 0 else 0.0          # int32 ops/s (= required bytes/s)
     traffic = measured_traffic(CONFIGS[a.config]["name"])
+    # LDS increments of the counting step: one per sample of each executed
+    # test (operand bytes / (d + 2) columns); the contraction paths count on
+    # MFMA and have none.  Peak: this device's own rate (bns_lds_increment_rate).
+    lds_peak = bns.bns_lds_increment_rate(0)[0]
+    incs_d = [tot[d]["operand_bytes"] / (d + 2) if tot[d]["test_group"] != 3 else 0.0 for d in range(launches)]
     per_depth = []
     for d in range(min(launches, ndep)):
         sd = span_d[d]
@@ -407,7 +412,10 @@ def main():
             "operand_gbs_required": req_bytes_d[d] / sd / 1e9 if sd > 0 else None,
             "lanes_per_test": {1: "wave", 2: "workgroup", 3: "Gram contraction"}.get(tot[d]["test_group"]),
             "chunks": tot[d]["chunks"], "chunk_samples": tot[d]["chunk_samples"],
+            "lds_frac": (incs_d[d] / sd) / lds_peak if (lds_peak and sd > 0 and incs_d[d] > 0) else None,
         })
+    count_span = sum(span_d[d] for d in range(min(launches, ndep)) if incs_d[d] > 0)
+    lds_rate = sum(incs_d[:ndep]) / count_span if count_span > 0 else None
     stream_peak = None if a.no_stream_peak else streaming_read_peak_gbs(torch)
 
     out = {
@@ -477,6 +485,16 @@ def main():
             "streaming_read_peak_gbs": stream_peak,
             "frac_required_of_streaming_peak": (req_bytes / span / 1e9 / stream_peak)
             if (stream_peak and span > 0) else None,
+        },
+        # The counting step's own resource: one LDS increment per sample and
+        # executed test, against the increment rate measured on this device.
+        "lds_roof": {
+            "achieved": lds_rate / 1e12 if lds_rate else None,
+            "peak_measured": lds_peak / 1e12 if lds_peak else None,
+            "unit": "T LDS increments/s",
+            "frac": lds_rate / lds_peak if (lds_rate and lds_peak) else None,
+            "basis": "one LDS increment per sample of each executed test over the spans of the depths "
+                     "that count in LDS; peak: bns_lds_increment_rate on this device",
         },
     }
 

@@ -373,6 +373,19 @@ bns_status bns_autotune(const bns_dataset *const *ds, int32_t n_problems, const 
                         const int32_t *max_depth, const bns_options *base, int32_t trials,
                         bns_options *best);
 
+/* Measures the device's LDS increment throughput: a reference for reports on
+ * the counting step (Section IV-A, step (i)), whose work is one increment of
+ * an LDS table word per sample and test; not used by the search.  Four
+ * workgroups of 256 lanes per compute unit add 1 to words of an LDS table,
+ * the lanes of a wave on different words (as the lane-interleaved replicas
+ * of the counting tables), about 17 G increments, timed with events on the
+ * library's stream of the device (a few ms; the call returns when they are
+ * done).  per_second (required): increments per second over the device;
+ * per_cu_per_clock (may be NULL): the same per compute unit and cycle of the
+ * device's reported peak clock.  Errors: BNS_E_INVALID_ARG (NULL
+ * per_second), BNS_E_DEVICE (a HIP call failed). */
+bns_status bns_lds_increment_rate(int32_t device, double *per_second, double *per_cu_per_clock);
+
 int32_t bns_skeleton_n_vars(const bns_skeleton *sk);
 
 /* adj: n_vars * n_vars uint8, adj[i * n + j] = 1 iff edge i - j survived. */

@@ -36,6 +36,7 @@ from ._lib import (  # noqa: F401
     bns_ci_batch,
     bns_ci_batch_noalloc,
     bns_ci_pairs,
+    bns_lds_increment_rate,
     bns_dataset_create,
     bns_dataset_wrap_device,
     bns_options,

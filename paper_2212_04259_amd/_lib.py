@@ -37,7 +37,7 @@ EXPORTS = [
     "bns_pc_skeleton_batch", "bns_skeleton_n_vars", "bns_skeleton_adjacency",
     "bns_skeleton_sepset", "bns_skeleton_removals", "bns_skeleton_stats", "bns_skeleton_free",
     "bns_autotune", "bns_ci_batch_noalloc", "bns_skeleton_orient", "bns_skeleton_create",
-    "bns_ci_pairs",
+    "bns_ci_pairs", "bns_lds_increment_rate",
 ]
 NOALLOC_SCRATCH_BYTES = 16 << 20
 
@@ -140,6 +140,8 @@ def load():
     L.bns_skeleton_create.argtypes = [i32, vp, vp, vp, vp, i64, P(vp)]
     L.bns_skeleton_orient.restype = i32
     L.bns_skeleton_orient.argtypes = [vp, vp]
+    L.bns_lds_increment_rate.restype = i32
+    L.bns_lds_increment_rate.argtypes = [i32, P(dbl), P(dbl)]
     L.bns_skeleton_free.restype = None
     L.bns_skeleton_free.argtypes = [vp]
     _lib = L
@@ -153,6 +155,14 @@ def _check(st: int):
 
 def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def bns_lds_increment_rate(device: int = 0):
+    """(increments per second, per compute unit per clock) of the device's LDS
+    (bns_lds_increment_rate)."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _check(load().bns_lds_increment_rate(int(device), ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def bns_options_default(**kw) -> bns_options:

@@ -800,6 +800,45 @@ extern "C" bns_status bns_ci_pairs(const bns_dataset *ds, double alpha, const bn
 // Skeleton results
 // ---------------------------------------------------------------------------
 
+extern "C" bns_status bns_lds_increment_rate(int32_t device, double *per_second, double *per_cu_per_clock) {
+    if (!per_second) return fail(BNS_E_INVALID_ARG, "per_second is NULL");
+    DevCtx *dc = nullptr;
+    bns_status st = get_ctx(device, &dc);
+    if (st != BNS_OK) return st;
+    DeviceGuard dg(device);
+    if (!dg.ok) return fail(BNS_E_DEVICE, "cannot select device %d", device);
+    std::lock_guard<std::mutex> lk(dc->mu);
+    hipStream_t s = dc->stream;
+    int clk_khz = 0;
+    HIP_TRY(hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeClockRate, device));
+    DevBuf sink;
+    HIP_TRY(sink.ensure(sizeof(unsigned int)));
+    const int grid = 4 * dc->num_cu, steps = 4096;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    struct EvFree {
+        hipEvent_t &a, &b;
+        ~EvFree() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } evf{e0, e1};
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(launch_lds_rate(grid, steps / 8, sink.as<unsigned int>(), s));  // warm-up
+    HIP_TRY(hipEventRecord(e0, s));
+    HIP_TRY(launch_lds_rate(grid, steps, sink.as<unsigned int>(), s));
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (!(ms > 0.0f)) return fail(BNS_E_DEVICE, "the measurement took no time");
+    const double incs = (double)grid * kWG * (double)steps * 16.0;
+    *per_second = incs / (ms * 1e-3);
+    if (per_cu_per_clock)
+        *per_cu_per_clock = clk_khz > 0 ? *per_second / dc->num_cu / (clk_khz * 1e3) : 0.0;
+    return BNS_OK;
+}
+
 extern "C" int32_t bns_skeleton_n_vars(const bns_skeleton *sk) { return sk ? sk->n : 0; }
 
 extern "C" bns_status bns_skeleton_adjacency(const bns_skeleton *sk, uint8_t *adj) {

@@ -179,6 +179,9 @@ inline int depth_units(const DepthArgs &a, int d) {
     return 0;
 }
 hipError_t launch_depth_apply(const DepthArgs &a, hipStream_t s);     // removals + finalize
+// LDS increment throughput: grid workgroups of kWG lanes, 16 * steps
+// increments per lane; sink receives the increments' total.
+hipError_t launch_lds_rate(int grid, int steps, unsigned int *sink, hipStream_t s);
 hipError_t launch_init_search(const DepthArgs &a, hipStream_t s);     // complete graph, reset
 hipError_t launch_publish(const DepthArgs &a, hipStream_t s);         // results into pinned host memory
 // Depth 0 through the pair contraction: Gram tiles, then one decision per pair

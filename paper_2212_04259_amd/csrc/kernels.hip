@@ -2365,4 +2365,42 @@ hipError_t launch_validate(const uint8_t *data, int64_t ld, int64_t m, int32_t n
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// LDS increment throughput (a reference for reports on the counting step,
+// not part of the search): every lane adds 1 to words of an LDS table,
+// sixteen increments per step, the lanes of a wave on different words
+// (word = cell * 64 + lane, as the lane-interleaved replicas of a table).
+// ---------------------------------------------------------------------------
+constexpr int kRateWords = 8192;
+
+__global__ __launch_bounds__(kWG) void k_lds_rate(int steps, unsigned int *sink) {
+    __shared__ uint32_t tab[kRateWords];
+    for (int i = threadIdx.x; i < kRateWords; i += kWG) tab[i] = 0u;
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t a[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const uint32_t h = (threadIdx.x * 2654435761u) ^ ((uint32_t)u * 40503u) ^ (blockIdx.x * 97u);
+        a[u] = (((h >> 7) & 63u) << 6) | lane;
+    }
+    const uint32_t base = lds_offset(tab);
+    for (int it = 0; it < steps; ++it) {
+        const uint32_t off = ((uint32_t)it << 6) & (kRateWords - 1);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) lds_inc(base + 4u * ((a[u] + off) & (kRateWords - 1)));
+    }
+    __syncthreads();
+    // the table's total (every increment) leaves the kernel, once per wave
+    unsigned long long s = 0;
+    for (int i = threadIdx.x; i < kRateWords; i += kWG) s += tab[i];
+    s = wave_sum(s);
+    if (lane == 0) atomicAdd(sink, (unsigned int)s);
+}
+
+hipError_t launch_lds_rate(int grid, int steps, unsigned int *sink, hipStream_t s) {
+    hipLaunchKernelGGL(k_lds_rate, dim3(grid), dim3(kWG), 0, s, steps, sink);
+    return hipGetLastError();
+}
+
 }  // namespace bns
