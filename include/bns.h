@@ -358,7 +358,8 @@ bns_status bns_pc_skeleton_batch(const bns_dataset *const *ds, int32_t n_problem
  *      16384, never} x units_per_group in {default, 4, 16};
  *   4. depth 1's work units (one test, or one edge's ranks of a level) and
  *      its path (the test kernel or the masked contractions);
- *   5. the depth-0 path (the test kernel or the pair contraction).
+ *   5. the depth-0 path (the test kernel or the pair contraction);
+ *   6. tests per grab again, then step 1 again, under the paths of 4 and 5.
  * A candidate is kept only if the whole search gets clearly faster.  *best
  * receives base with the chosen options filled in (base NULL = defaults).
  * The choice is cached per device (architecture and compute units) and

@@ -2022,6 +2022,26 @@ extern "C" bns_status bns_autotune(const bns_dataset *const *ds, int32_t n_probl
             }
         }
     }
+    // The grab size again, and the groups per depth, under the paths chosen
+    // last: edge units or contractions change the depth that dominated the
+    // grid's searches.
+    if (!o.tickets_per_grab) {
+        const bns_options start3 = cur;
+        for (int32_t g : grab_opts) {
+            bns_options c = start3;
+            c.tickets_per_grab = g;
+            if (std::memcmp(&c, &cur, sizeof(c)) == 0) continue;
+            double t = 0.0;
+            st = timed(c, &t);
+            if (st != BNS_OK) return st;
+            if (t < cur_t * 0.98) {
+                cur = c;
+                cur_t = t;
+            }
+        }
+        st = try_depths();
+        if (st != BNS_OK) return st;
+    }
     *best = cur;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune.push_back(TuneEntry{device, key, cur});
