@@ -442,8 +442,12 @@ BNS_INLINE void levels_wave(const DepthArgs &A, Ctl *c, const unsigned int *hist
         // Grabs of several units amortise the decode latency when there is
         // work for many rounds; a group holds its batch, so larger batches
         // also run more tests before earlier ranks of their edges finish
-        // (speculation): one unit per grab per eight rounds of all groups.
-        const unsigned long long per = total * C / (8ull * groups);
+        // (speculation) and leave more work with one group at the end of
+        // the depth: one unit per grab per eight rounds of all groups for
+        // workgroups, per 32 rounds for waves (a wave's test takes four times
+        // as long, and a batch of tests of very different lengths, as in a
+        // batch of datasets, ends late).
+        const unsigned long long per = total * C / ((mode ? 8ull : 32ull) * groups);
         c->batch = A.grab_fixed > 0 ? A.grab_fixed
                                     : (int)max(1ull, min(per, (unsigned long long)kSlotsPerWave));
         if (done_lds) *done_lds = (total == 0 || any_bad) ? 1 : 0;
