@@ -1076,8 +1076,9 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     // The automatic choice is the test kernel: the contraction evaluates every
     // depth-1 test, where the sequential order stops each edge at its first
     // accepting one (3x to 10x fewer tests on the measured workloads), and
-    // each tile streams its variables' columns again (cfg4: 4.0 M tests and
-    // 103 GB of column reads against 0.38 M tests in the test kernel).
+    // each tile streams its variables' columns again (1,000 variables x
+    // 200,000 samples: 4.0 M tests and 103 GB of column reads against 0.38 M
+    // tests in the test kernel).
     if (!verify && o.form == BNS_FORM_BATCHED && (unbounded || dmax >= 1) && o.depth1 == BNS_DEPTH1_GRAM) {
         bool cards_ok = true;
         for (int32_t k = 0; k < P; ++k)

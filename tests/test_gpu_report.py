@@ -113,7 +113,7 @@ def test_workspace_limit(bns):
     with pytest.raises(bns.BnsError) as ei:
         bns.bns_pc_skeleton_dataset(h, ds.alpha, ds.max_depth, bns.bns_options_default(workspace_mb=1))
     assert ei.value.status == 4 and "workspace" in str(ei.value)
-    # the split-merge tables alone take 32 MiB; 256 MiB is enough for cfg2
+    # the split-merge tables alone take 32 MiB; 256 MiB is enough for the 60-variable workload
     got = bns.bns_pc_skeleton_dataset(h, ds.alpha, ds.max_depth, bns.bns_options_default(workspace_mb=256))
     compare_skeleton(got, load_golden(2)["datasets"][0], "cfg2 workspace 256 MiB")
     tests = [(0, 1, ())] * 100_000
