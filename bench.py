@@ -152,6 +152,21 @@ def measured_traffic(workload):
     return rec.get("hbm_bytes_per_launch")
 
 
+def measured_l2_hit_rates(workload):
+    """Per-depth L2 hit rates (rocprofv3 TCC_HIT / (TCC_HIT + TCC_MISS)) from
+    the committed counter summary of this workload, or None as for
+    measured_traffic."""
+    path = os.path.join(ROOT, "profiles", f"k_depth_tests_{workload}_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    rates = [p.get("l2_hit_rate") for p in rec.get("per_depth", [])]
+    return rates if any(r is not None for r in rates) else None
+
+
 def streaming_read_peak_gbs(torch, gib=4, reps=10):
     """Device read bandwidth of this machine: float reductions (sum, max) over a
     buffer far larger than the last-level cache (GB/s, best of reps and of
@@ -435,6 +450,7 @@ def main():
     req_bytes = sum(req_bytes_d)
     ops_rate = req_bytes / span if span > 0 else 0.0          # int32 ops/s (= required bytes/s)
     traffic = measured_traffic(CONFIGS[a.config]["name"])
+    l2_hit = measured_l2_hit_rates(CONFIGS[a.config]["name"])
     # LDS increments of the counting step: one per sample of each executed
     # test (operand bytes / (d + 2) columns); the contraction paths count on
     # MFMA and have none.  Peak: this device's own rate (bns_lds_increment_rate).
@@ -520,6 +536,7 @@ def main():
             "l2_egress_gbs": (traffic / (span / launches) / 1e9) if (traffic and span > 0) else None,
             "l2_egress_frac_hbm": (traffic / (span / launches) / 1e9 / HBM_PEAK_GBS)
             if (traffic and span > 0) else None,
+            "l2_hit_rate_per_depth": l2_hit,
             "streaming_read_peak_gbs": stream_peak,
             "frac_required_of_streaming_peak": (req_bytes / span / 1e9 / stream_peak)
             if (stream_peak and span > 0) else None,
