@@ -30,9 +30,16 @@ BNS_INLINE u32x4 onehot16(u32x4 w, uint32_t plo, uint32_t phi, uint32_t cat, boo
             const uint32_t t = ~(((d & 0x7f7f7f7fu) + 0x7f7f7f7fu) | d | 0x7f7f7f7fu);
             r = t >> 7;
         }
-        const int vk = nvalid - 4 * k;
-        const uint32_t keep = vk >= 4 ? 0xffffffffu : vk <= 0 ? 0u : ((1u << (8 * vk)) - 1u);
-        o[k] = r & keep;
+        o[k] = r;
+    }
+    // (only the last group of a chunk is partial: whole groups skip the masks)
+    if (nvalid < 16) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int vk = nvalid - 4 * k;
+            const uint32_t keep = vk >= 4 ? 0xffffffffu : vk <= 0 ? 0u : ((1u << (8 * vk)) - 1u);
+            o[k] &= keep;
+        }
     }
     return o;
 }

@@ -102,10 +102,11 @@ __global__ __launch_bounds__(kGramWG) void k_gram(PairArgs P, Ctl *c) {
         u32x4 pv[kPer];
         int pn[kPer];
         auto load = [&](int64_t s) {
+            // samples left from s (uniform; at most a step and a group matter)
+            const int left = (int)min(s1 - s, (int64_t)(kGramKS + 16));
 #pragma unroll
             for (int r = 0; r < kPer; ++r) {
-                const int64_t ss = s + 16 * ((tid + kGramWG * r) % kGramQS);
-                pn[r] = (int)max((int64_t)0, min((int64_t)16, s1 - ss));
+                pn[r] = min(16, max(0, left - 16 * ((tid + kGramWG * r) % kGramQS)));
                 pv[r] = u32x4{0u, 0u, 0u, 0u};
                 if (act[r] && colp[r] && pn[r] > 0) pv[r] = *(const u32x4 *)(colp[r] + s);
             }
