@@ -19,18 +19,17 @@ constexpr int kGramWG = 256;
 // wider ones an exact zero-byte test of w ^ cat.
 BNS_INLINE u32x4 onehot16(u32x4 w, uint32_t plo, uint32_t phi, uint32_t cat, bool wide, int nvalid) {
     u32x4 o;
+    // (one branch for the four words: the wide form is rare)
+    if (!wide) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint32_t x = w[k];
-        uint32_t r;
-        if (!wide) {
-            r = __builtin_amdgcn_perm(phi, plo, x);
-        } else {
-            const uint32_t d = x ^ (cat * 0x01010101u);
+        for (int k = 0; k < 4; ++k) o[k] = __builtin_amdgcn_perm(phi, plo, w[k]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t d = w[k] ^ (cat * 0x01010101u);
             const uint32_t t = ~(((d & 0x7f7f7f7fu) + 0x7f7f7f7fu) | d | 0x7f7f7f7fu);
-            r = t >> 7;
+            o[k] = t >> 7;
         }
-        o[k] = r;
     }
     // (only the last group of a chunk is partial: whole groups skip the masks)
     if (nvalid < 16) {

@@ -108,7 +108,9 @@ __global__ __launch_bounds__(kGramWG) void k_gram(PairArgs P, Ctl *c) {
             for (int r = 0; r < kPer; ++r) {
                 pn[r] = min(16, max(0, left - 16 * ((tid + kGramWG * r) % kGramQS)));
                 pv[r] = u32x4{0u, 0u, 0u, 0u};
-                if (act[r] && colp[r] && pn[r] > 0) pv[r] = *(const u32x4 *)(colp[r] + s);
+                // (a global load: a flat one would also count against the
+                // LDS counter, and the step's LDS reads would wait for it)
+                if (act[r] && colp[r] && pn[r] > 0) pv[r] = *(const gvec4 *)(colp[r] + s);
             }
         };
         auto store = [&](int buf) {
