@@ -341,7 +341,7 @@ __global__ __launch_bounds__(kGramWG) __attribute__((amdgpu_waves_per_eu(2))) vo
                     const int64_t ss = s + 16 * q;
                     const int64_t nv = s1 - ss;
                     if (nv > 0) {
-                        pv[r] = *(const u32x4 *)(slot_col[sl] + ss);
+                        pv[r] = *(const gvec4 *)(slot_col[sl] + ss);  // (global, not flat)
                         if (nv < 16) {
                             // samples past the chunk's end: no category
 #pragma unroll
@@ -375,15 +375,21 @@ __global__ __launch_bounds__(kGramWG) __attribute__((amdgpu_waves_per_eu(2))) vo
             const int buf = st & 1;
             const bool more = st + 1 < nsteps;
             if (more) load(s0 + (int64_t)(st + 1) * kTriKS);
-            const uint8_t *Ra = slotA >= 0 ? &raw[buf][slotA][0] : nullptr;
-            const uint8_t *Rb = slotB >= 0 ? &raw[buf][slotB][0] : nullptr;
-            const uint8_t *Ru = &raw[buf][slotU][0];
+            // LDS views of the staged rows (LDS reads, not flat ones: a flat
+            // read also waits for the step's outstanding global loads)
+            typedef __attribute__((address_space(3))) const u32x4 lvec4;
+            const uint32_t raw_lo = lds_offset(reinterpret_cast<const uint32_t *>(&raw[buf][0][0]));
+            const uint32_t Ra = raw_lo + (uint32_t)(slotA >= 0 ? slotA : 0) * kTriRow;
+            const uint32_t Rb = raw_lo + (uint32_t)(slotB >= 0 ? slotB : 0) * kTriRow;
+            const uint32_t Ru = raw_lo + (uint32_t)slotU * kTriRow;
 #pragma unroll 2
             for (int kk = 0; kk < kTriKS / 32; ++kk) {
                 const int koff = 32 * kk + 16 * (lane >> 5);
-                const v4i af = Ra ? onehot_perm(*(const u32x4 *)(Ra + koff), aplo, aphi) : v4i{0, 0, 0, 0};
-                const v4i bf = Rb ? onehot_perm(*(const u32x4 *)(Rb + koff), bplo, bphi) : v4i{0, 0, 0, 0};
-                const u32x4 uw = *(const u32x4 *)(Ru + koff);
+                const u32x4 wa = *(const lvec4 *)(uintptr_t)(Ra + koff);
+                const u32x4 wb = *(const lvec4 *)(uintptr_t)(Rb + koff);
+                const u32x4 uw = *(const lvec4 *)(uintptr_t)(Ru + koff);
+                const v4i af = slotA >= 0 ? onehot_perm(wa, aplo, aphi) : v4i{0, 0, 0, 0};
+                const v4i bf = slotB >= 0 ? onehot_perm(wb, bplo, bphi) : v4i{0, 0, 0, 0};
 #pragma unroll
                 for (int cc = 0; cc < kTriCats; ++cc) {
                     if (cc >= nc) break;  // uniform
