@@ -1,5 +1,5 @@
 """Host-side logic of bench.py (no GPU): the one-GPU contract and the guard on
-the committed HBM-traffic figures."""
+the committed HBM-traffic and L2 hit-rate figures."""
 
 import json
 import os
@@ -49,3 +49,25 @@ def test_committed_counter_summaries_are_well_formed():
         assert rec["kernel"] == "k_depth_tests"
         assert rec["hbm_bytes_per_launch"] > 0
         assert len(rec["kernel_sources_sha256"]) == 64
+        # L2 hit rates (a separate counter run), when present, are fractions
+        for p in rec["per_depth"]:
+            if p.get("l2_hit_rate") is not None:
+                assert 0.0 <= p["l2_hit_rate"] <= 1.0
+                assert "l2_hit" in rec["commands"]
+
+
+def test_l2_hit_rates_follow_the_kernel_digest(tmp_path, monkeypatch):
+    import bench
+    assert bench.measured_l2_hit_rates("no_such_workload") is None
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    good = bench.kernel_sources_sha256()
+    rec = dict(kernel="k_depth_tests", workload="w", hbm_bytes_per_launch=1.0, kernel_sources_sha256=good,
+               per_depth=[dict(depth=0, l2_hit_rate=0.5), dict(depth=1, l2_hit_rate=0.25)])
+    (prof / "k_depth_tests_w_counters.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_sources_sha256", lambda: good)
+    assert bench.measured_l2_hit_rates("w") == [0.5, 0.25]
+    rec["kernel_sources_sha256"] = "0" * 64
+    (prof / "k_depth_tests_w_counters.json").write_text(json.dumps(rec))
+    assert bench.measured_l2_hit_rates("w") is None
