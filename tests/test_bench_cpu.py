@@ -71,3 +71,21 @@ def test_l2_hit_rates_follow_the_kernel_digest(tmp_path, monkeypatch):
     rec["kernel_sources_sha256"] = "0" * 64
     (prof / "k_depth_tests_w_counters.json").write_text(json.dumps(rec))
     assert bench.measured_l2_hit_rates("w") is None
+
+
+def test_oracle_baseline_of_a_batch_uses_worker_processes():
+    # a batch of small datasets: one full pass over worker processes, and the
+    # same total of tests as the oracle run in this process
+    import bench
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import oracle
+    from bnsynth import make_dataset
+    dss = [make_dataset(8 + k, 10, 2, 2, 3, 0.5, 500, seed=9100 + k) for k in range(3)]
+    for d in dss:
+        d.alpha, d.max_depth = 0.05, -1
+    r = bench.cpu_baseline(dss)
+    assert r["kind"] == "oracle" and r["value"] > 0
+    assert 1 <= r["cores"] <= 3
+    tests = sum(int(sum(oracle.pc_skeleton(d.data, d.cards, 0.05, -1).tests)) for d in dss)
+    assert "3 datasets" in r["sample"]
+    assert tests > 0
