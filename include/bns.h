@@ -189,9 +189,9 @@ enum {
 /* Work units of depth 1 in the test kernel (the counterpart of Section IV-B's
  * group of tests of one edge). */
 enum {
-    BNS_GROUP_AUTO = 0,   /* EDGE when some dataset's columns (variables x samples bytes)
-                             exceed 64 MiB, a quarter of MI355X's last-level cache (its tests
-                             would re-read X and Y from DRAM), else TEST */
+    BNS_GROUP_AUTO = 0,   /* EDGE when the search's columns (variables x samples bytes of
+                             all its datasets) exceed 64 MiB, a quarter of MI355X's last-level
+                             cache (its tests would re-read X and Y from DRAM), else TEST */
     BNS_GROUP_TEST = 1,   /* one test per work unit */
     BNS_GROUP_EDGE = 2    /* one edge's ranks of a work-queue level per unit, counted in one
                              pass over the samples that loads X and Y once and adds each

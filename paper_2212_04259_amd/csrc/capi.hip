@@ -1229,14 +1229,13 @@ static bns_status run_batched(DevCtx &dc, const bns_dataset *const *ds, int32_t 
     a.round_width = o.round_tests;
     a.edge_form = o.form == BNS_FORM_EDGE ? 1 : 0;
     // depth 1 in (edge, level) units: doubling levels, batched form, not in
-    // verification mode; automatic for datasets whose columns exceed a
-    // quarter of the last-level cache (their tests re-read X and Y from
-    // DRAM: 1,000 variables x 200,000 samples ran depth 1 in 14.7 instead of
-    // 23.1 ms); smaller ones keep one test per unit, whose rank-major order
-    // skips more speculative tests (60 x 50,000: 204 against 143 us)
-    double nm_max = 0.0;
-    for (int32_t k = 0; k < P; ++k) nm_max = std::max(nm_max, (double)ds[k]->n * (double)ds[k]->m);
-    const bool xy_want = o.group_tests == BNS_GROUP_EDGE || (o.group_tests == BNS_GROUP_AUTO && nm_max > kGrabRunBytes);
+    // verification mode; automatic when the search's columns (all its
+    // datasets') exceed a quarter of the last-level cache (their tests re-read
+    // X and Y from DRAM: 1,000 variables x 200,000 samples ran depth 1 in 14.7
+    // instead of 23.1 ms, the 64-dataset batch in 9.3 instead of 12.3 ms);
+    // smaller searches keep one test per unit, whose rank-major order skips
+    // more speculative tests (60 x 50,000: 204 against 143 us)
+    const bool xy_want = o.group_tests == BNS_GROUP_EDGE || (o.group_tests == BNS_GROUP_AUTO && col_bytes > kGrabRunBytes);
     a.xy_policy = (xy_want && o.form == BNS_FORM_BATCHED && o.round_tests == 0 && !verify && (unbounded || dmax >= 1))
                       ? 1 : 0;
     a.grab_fixed = o.tickets_per_grab;
